@@ -1,0 +1,208 @@
+/*
+ * sssp.h - C ABI of the MI355X (gfx950) stepping-SSSP library, libsssp.so.
+ *
+ * The library solves single-source shortest paths on directed graphs with
+ * non-negative integer weights by the stepping-algorithm framework of Dong,
+ * Gu, Sun and Zhang, "Efficient Stepping Algorithms and Implementations for
+ * Parallel Shortest Paths" (SPAA 2021):
+ *
+ *   Sec. 3.2, Alg. 1: delta[.] = inf; delta[s] = 0; Update(s);
+ *                     while |Q| > 0: theta = ExtDist; for u in Extract(theta):
+ *                     for v in N(u): if WriteMin(delta[v], delta[u] + w(u,v)):
+ *                     Update(v).
+ *   Sec. 3.1, Table 1: the lazy-batched priority queue (LaB-PQ) interface:
+ *                     Update(id) marks id as (re)inserted with key delta[id];
+ *                     Extract(theta) returns and removes every id whose key
+ *                     is <= theta, and never runs concurrently with Update.
+ *   Sec. 4.3:         the flat-array LaB-PQ (one flag per vertex, Extract
+ *                     scans and packs), realised here as a device bitmap
+ *                     plus an explicit frontier list while the queue is small
+ *                     (the sparse/dense optimisation of Sec. 6).
+ *   Table 2:          the threshold rules (rho-stepping, Delta*-stepping,
+ *                     Bellman-Ford; theta = min for tests).
+ *
+ * The whole loop runs in one persistent kernel per source, without host
+ * round trips between steps. All distance arithmetic is exact: weights are
+ * uint32, distances uint64, and an unreachable vertex reads UINT64_MAX.
+ *
+ * Conventions for every entry point:
+ *   - Functions return an sssp_status; nothing aborts, throws or exits.
+ *   - On error, sssp_last_error() returns a thread-local detail string.
+ *   - "Device pointer" means memory allocated on the current HIP device
+ *     (hipMalloc or a torch tensor on that device); "host pointer" means
+ *     ordinary process memory.
+ *   - Streams are hipStream_t values passed as void*; NULL is the default
+ *     stream.
+ */
+#ifndef SSSP_H
+#define SSSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SSSP_ABI_VERSION 1
+
+typedef enum {
+  SSSP_OK = 0,
+  SSSP_ERR_INVALID_ARGUMENT = 1, /* a NULL pointer, a bad size, rule or parameter */
+  SSSP_ERR_INVALID_GRAPH = 2,    /* CSR arrays violate the rules of sssp_graph_create */
+  SSSP_ERR_OUT_OF_MEMORY = 3,    /* a device allocation failed */
+  SSSP_ERR_NO_DEVICE = 4,        /* no HIP device, or it cannot run a cooperative launch */
+  SSSP_ERR_DEVICE = 5,           /* a HIP runtime call or the kernel failed */
+  SSSP_ERR_STEP_LIMIT = 6,       /* params.max_steps steps ran and the queue is not empty */
+  SSSP_ERR_UNSUPPORTED = 7       /* a valid request this build does not implement */
+} sssp_status;
+
+/* Threshold rules (ExtDist of Alg. 1; Table 2). Every rule yields the same
+ * distance array; they differ in steps and work only. */
+typedef enum {
+  /* rho-stepping (Sec. 3.2 and Sec. 6): theta = the rho-th smallest key in Q,
+   * estimated from s = ceil(10 * (q / rho + log q)) uniform samples of the
+   * queue, log q = 1 + log2(q + 1), taking the ceil(rho * s / q)-th smallest
+   * (App. B, c = 10). If q <= rho the whole queue is extracted. The first two
+   * steps that scan the bitmap use floor(rho / 10) instead of rho (Sec. 6). */
+  SSSP_RULE_RHO = 0,
+  /* Delta*-stepping (Table 2, Thm. 5.5): theta = i * Delta, i = 1, 2, ...
+   * advancing every step, skipping ahead to ceil(min key / Delta) when the
+   * buckets in between are empty. */
+  SSSP_RULE_DELTA_STAR = 1,
+  /* Bellman-Ford (Table 2): theta = +inf, every queued vertex each step. */
+  SSSP_RULE_BF = 2,
+  /* theta = the minimum key in Q (Table 2, Dijkstra row). Sequential by
+   * nature; provided so tests can pin exact step counts. */
+  SSSP_RULE_MIN = 3
+} sssp_rule;
+
+typedef enum { SSSP_OFFSETS_I32 = 0, SSSP_OFFSETS_I64 = 1 } sssp_offset_width;
+
+/* sssp_graph_create flags */
+#define SSSP_INPUT_HOST 0x1u   /* offsets/targets/weights are host pointers */
+#define SSSP_INPUT_DEVICE 0x2u /* offsets/targets/weights are device pointers */
+#define SSSP_TRUST_INPUT 0x4u  /* skip CSR validation (caller guarantees it) */
+
+/* Tuning knobs. Zero in any field selects the library default. None of them
+ * changes the distances; they change speed, steps and work only. */
+typedef struct {
+  uint32_t blocks_per_cu; /* workgroups per compute unit in the persistent grid
+                             (clamped to what can be co-resident) */
+  uint32_t hub_degree;    /* out-degree above which a frontier vertex's edges are
+                             split into chunks shared by many workgroups */
+  uint32_t chunk_edges;   /* edges per hub chunk */
+  uint32_t list_divisor;  /* keep an explicit frontier list while |Q| <= n / list_divisor;
+                             0xFFFFFFFF disables the list (bitmap scans only) */
+  uint32_t sample_cap;    /* maximum rho-stepping sample size */
+  uint32_t probe_cap;     /* maximum bitmap probes per sampled step */
+  uint32_t no_filter;     /* 1 = skip the read-before-atomic filter in Relax */
+  uint32_t reserved;
+} sssp_tuning;
+
+/* One record per step, written when params.trace is set. */
+typedef struct {
+  uint64_t theta;     /* threshold used by Extract (UINT64_MAX = +inf) */
+  uint64_t q;         /* |Q| before Extract */
+  uint64_t extracted; /* vertices returned by Extract */
+  uint64_t edges;     /* arcs relaxed (out-degree sum of the extracted vertices) */
+  uint64_t successes; /* WriteMin calls that lowered a distance */
+  uint32_t flags;     /* bit 0: Extract scanned the bitmap (else the list);
+                         bit 1: an explicit list was built for the next step;
+                         bit 2: theta came from sampling */
+  uint32_t samples;   /* sample size when bit 2 is set */
+} sssp_step_record;
+
+typedef struct {
+  uint32_t rule;      /* sssp_rule */
+  uint32_t reserved0;
+  uint64_t rho;       /* SSSP_RULE_RHO: rho >= 1 */
+  uint64_t delta;     /* SSSP_RULE_DELTA_STAR: Delta >= 1 */
+  uint64_t seed;      /* sampling seed (rho rule); affects steps and work only */
+  uint64_t max_steps; /* 0 = unlimited; else stop with SSSP_ERR_STEP_LIMIT */
+  const sssp_tuning* tuning; /* host pointer or NULL for defaults */
+  /* Optional device pointer, n uint32 entries per source (row-major like
+   * dist): entry v is incremented each time v is extracted. The caller
+   * zeroes it. NULL disables counting. */
+  uint32_t* extract_counts;
+  /* Optional device pointer to trace_capacity records (first source only);
+   * steps beyond the capacity are not recorded. NULL disables tracing. */
+  sssp_step_record* trace;
+  uint64_t trace_capacity;
+} sssp_params;
+
+typedef struct {
+  uint64_t steps;            /* loop iterations (sum over sources) */
+  uint64_t extracted;        /* sum of |Extract| over steps */
+  uint64_t edges_relaxed;    /* arcs relaxed, counting repeats */
+  uint64_t writemin_success; /* WriteMin calls that lowered a distance */
+  uint64_t dense_steps;      /* steps whose Extract scanned the bitmap */
+  uint64_t sampled_steps;    /* rho steps whose threshold came from sampling */
+  double device_ms;          /* GPU time of the solve kernels, HIP events */
+} sssp_stats;
+
+typedef struct sssp_graph sssp_graph; /* opaque */
+
+/* Fill *p with defaults: rule = RHO, rho = 2^20, delta = 2^13, seed = 1,
+ * unlimited steps, default tuning, no counters, no trace. */
+void sssp_default_params(sssp_params* p);
+
+/*
+ * Create a graph on the current HIP device from CSR arrays (Sec. 2 graph
+ * notation: arcs (u, v) with weight w(u, v) >= 0; N(u) = row u).
+ *   n        number of vertices, 1 <= n < 2^31.
+ *   m        number of arcs, 0 <= m < 2^40.
+ *   ow       width of `offsets` entries (SSSP_OFFSETS_I32 needs m < 2^31).
+ *   offsets  n + 1 entries: offsets[0] = 0, non-decreasing, offsets[n] = m.
+ *            Row u holds arcs offsets[u] .. offsets[u+1]-1.
+ *   targets  m int32 entries in [0, n).
+ *   weights  m uint32 entries (zero allowed). Parallel arcs and self-loops
+ *            are allowed.
+ *   flags    exactly one of SSSP_INPUT_HOST / SSSP_INPUT_DEVICE, optionally
+ *            SSSP_TRUST_INPUT.
+ *   stream   stream for the upload (the call returns after it completes).
+ * The library copies the arrays into its own device layout; the caller keeps
+ * ownership of its arrays and may free them on return. Errors:
+ * INVALID_ARGUMENT, INVALID_GRAPH (validation failed; detail names the first
+ * offending index), OUT_OF_MEMORY, NO_DEVICE, DEVICE. On error *out is NULL.
+ */
+sssp_status sssp_graph_create(int64_t n, int64_t m, sssp_offset_width ow, const void* offsets,
+                              const int32_t* targets, const uint32_t* weights, uint32_t flags, void* stream,
+                              sssp_graph** out);
+
+/* Release the graph and its device memory. NULL is accepted. Must not race a
+ * solve on the same graph. */
+sssp_status sssp_graph_destroy(sssp_graph* g);
+
+/* Query sizes: vertices, arcs and device bytes held (graph plus workspace). */
+sssp_status sssp_graph_info(const sssp_graph* g, int64_t* n, int64_t* m, uint64_t* device_bytes);
+
+/*
+ * Solve from each of n_src sources (Alg. 1 once per source).
+ *   sources  host array of n_src vertex ids in [0, n).
+ *   params   rule and parameters (see sssp_params); NULL = defaults.
+ *   dist     device pointer to n_src * n uint64 entries, row-major:
+ *            dist[i * n + v] = exact distance from sources[i] to v, or
+ *            UINT64_MAX if v is unreachable. Overwritten completely.
+ *   stream   stream the kernels run on; the call returns after they finish.
+ *   stats    host pointer or NULL; receives totals over all sources.
+ * The graph's workspace is reused, so calls on one graph must not overlap.
+ * Errors: INVALID_ARGUMENT (bad pointer, source, rule, rho = 0 or delta = 0),
+ * STEP_LIMIT (dist then holds upper bounds), DEVICE, OUT_OF_MEMORY.
+ */
+sssp_status sssp_solve(const sssp_graph* g, const int32_t* sources, int32_t n_src, const sssp_params* params,
+                       uint64_t* dist, void* stream, sssp_stats* stats);
+
+/* Static description of a status code. */
+const char* sssp_status_string(sssp_status s);
+
+/* Detail of the last error on this thread ("" if none). */
+const char* sssp_last_error(void);
+
+/* SSSP_ABI_VERSION of the loaded library. */
+int sssp_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSSP_H */

@@ -1,0 +1,179 @@
+"""MI355X (gfx950) stepping-algorithm SSSP.
+
+Python face of libsssp.so (include/sssp.h): load a CSR graph onto the GPU,
+pick a stepping rule (rho-stepping, Delta*-stepping, Bellman-Ford; Table 2 of
+Dong, Gu, Sun and Zhang, SPAA 2021) and solve into a uint64 distance array.
+PyTorch supplies device memory and the stream; every step of the loop runs in
+the library's HIP kernels.
+
+    import paper_2105_06145_amd as sp
+    g = sp.Graph.from_csr(offsets, targets, weights)       # numpy, host
+    dist, stats = sp.solve(g, [src], rule="rho", rho=1 << 20)
+    d = sp.to_numpy_u64(dist)                              # uint64, UINT64_MAX = unreachable
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _native as N
+from ._native import (SSSP_RULE_BF, SSSP_RULE_DELTA_STAR, SSSP_RULE_MIN, SSSP_RULE_RHO, sssp_abi_version,
+                      sssp_default_params, sssp_graph_create, sssp_graph_destroy, sssp_graph_info,
+                      sssp_last_error, sssp_params, sssp_solve, sssp_stats, sssp_status_string, sssp_step_record,
+                      sssp_tuning)
+
+__all__ = ["Graph", "solve", "SSSPError", "to_numpy_u64", "RULES", "INF", "sssp_graph_create", "sssp_graph_destroy",
+           "sssp_graph_info", "sssp_solve", "sssp_status_string", "sssp_last_error", "sssp_abi_version",
+           "sssp_default_params", "sssp_params", "sssp_stats", "sssp_tuning", "sssp_step_record"]
+
+INF = 0xFFFFFFFFFFFFFFFF
+RULES = {"rho": SSSP_RULE_RHO, "delta": SSSP_RULE_DELTA_STAR, "delta_star": SSSP_RULE_DELTA_STAR,
+         "bf": SSSP_RULE_BF, "min": SSSP_RULE_MIN}
+
+
+class SSSPError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {sssp_status_string(status)} ({sssp_last_error()})")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Graph:
+    """A CSR graph resident on the current GPU (owned by the library)."""
+
+    def __init__(self, handle, n: int, m: int):
+        self._h = handle
+        self.n = n
+        self.m = m
+
+    @classmethod
+    def from_csr(cls, offsets, targets, weights, validate: bool = True, stream=None) -> "Graph":
+        """offsets (n+1, int32 or int64), targets (m, int32), weights (m,
+        uint32): numpy arrays (host) or torch CUDA tensors (device). The
+        library copies them into its own layout."""
+        torch = _torch()
+        flags = 0 if validate else N.SSSP_TRUST_INPUT
+        if isinstance(offsets, torch.Tensor):
+            if not (offsets.is_cuda and targets.is_cuda and weights.is_cuda):
+                raise ValueError("torch inputs must be CUDA tensors")
+            ow = N.SSSP_OFFSETS_I64 if offsets.dtype == torch.int64 else N.SSSP_OFFSETS_I32
+            if offsets.dtype not in (torch.int32, torch.int64) or targets.dtype != torch.int32 or \
+                    weights.dtype not in (torch.int32, torch.uint32):
+                raise ValueError("dtypes: offsets int32/int64, targets int32, weights uint32 (or int32 bits)")
+            offsets, targets, weights = offsets.contiguous(), targets.contiguous(), weights.contiguous()
+            n = offsets.numel() - 1
+            m = targets.numel()
+            ptrs = [ctypes.c_void_p(t.data_ptr()) for t in (offsets, targets, weights)]
+            flags |= N.SSSP_INPUT_DEVICE
+            keep = (offsets, targets, weights)
+        else:
+            off = np.ascontiguousarray(offsets)
+            if off.dtype not in (np.int32, np.int64):
+                off = off.astype(np.int64)
+            ow = N.SSSP_OFFSETS_I64 if off.dtype == np.int64 else N.SSSP_OFFSETS_I32
+            tgt = np.ascontiguousarray(targets, dtype=np.int32)
+            w = np.ascontiguousarray(weights, dtype=np.uint32)
+            n = off.shape[0] - 1
+            m = tgt.shape[0]
+            ptrs = [ctypes.c_void_p(a.ctypes.data) for a in (off, tgt, w)]
+            flags |= N.SSSP_INPUT_HOST
+            keep = (off, tgt, w)
+        rc, h = sssp_graph_create(n, m, ow, ptrs[0], ptrs[1], ptrs[2], flags, _stream_ptr(stream))
+        del keep
+        if rc != N.SSSP_OK:
+            raise SSSPError(rc, "sssp_graph_create")
+        return cls(h, n, m)
+
+    def device_bytes(self) -> int:
+        rc, _, _, b = sssp_graph_info(self._h)
+        if rc != N.SSSP_OK:
+            raise SSSPError(rc, "sssp_graph_info")
+        return b
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            sssp_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_tuning(**kw) -> sssp_tuning:
+    t = sssp_tuning()
+    for k, v in kw.items():
+        setattr(t, k, int(v))
+    return t
+
+
+def solve(g: Graph, sources, rule: str = "rho", rho: int = 1 << 20, delta: int = 1 << 13, seed: int = 1,
+          max_steps: int = 0, tuning: dict | sssp_tuning | None = None, out=None, stream=None,
+          trace: int = 0, extract_counts: bool = False):
+    """Solve from each source. Returns (dist, stats) where dist is a torch
+    int64 CUDA tensor (n_src, n) holding uint64 bit patterns (-1 = unreachable)
+    and stats is a dict; with trace > 0 stats["trace"] holds per-step records,
+    with extract_counts=True stats["extract_counts"] a (n_src, n) int32 tensor."""
+    torch = _torch()
+    src = np.ascontiguousarray(np.atleast_1d(np.asarray(sources)), dtype=np.int32)
+    ns = int(src.shape[0])
+    if out is None:
+        out = torch.empty((ns, g.n), dtype=torch.int64, device="cuda")
+    elif out.dtype != torch.int64 or out.numel() != ns * g.n or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int64 CUDA tensor with n_src * n elements")
+    p = sssp_params()
+    N.lib().sssp_default_params(ctypes.byref(p))
+    p.rule = RULES[rule]
+    p.rho = int(rho)
+    p.delta = int(delta)
+    p.seed = int(seed)
+    p.max_steps = int(max_steps)
+    tun = None
+    if tuning is not None:
+        tun = tuning if isinstance(tuning, sssp_tuning) else make_tuning(**tuning)
+        p.tuning = ctypes.pointer(tun)
+    counts = None
+    if extract_counts:
+        counts = torch.zeros((ns, g.n), dtype=torch.int32, device="cuda")
+        p.extract_counts = counts.data_ptr()
+    tr = None
+    if trace > 0:
+        tr = torch.zeros((int(trace), ctypes.sizeof(sssp_step_record) // 8), dtype=torch.int64, device="cuda")
+        p.trace = tr.data_ptr()
+        p.trace_capacity = int(trace)
+    st = sssp_stats()
+    rc = sssp_solve(g._h, ctypes.c_void_p(src.ctypes.data), ns, p, ctypes.c_void_p(out.data_ptr()),
+                    _stream_ptr(stream), st)
+    if rc != N.SSSP_OK:
+        raise SSSPError(rc, "sssp_solve")
+    stats = st.as_dict()
+    if counts is not None:
+        stats["extract_counts"] = counts
+    if tr is not None:
+        raw = tr.cpu().numpy().view(np.uint64)
+        recs = []
+        for i in range(min(int(trace), int(stats["steps"]) if ns == 1 else int(trace))):
+            r = raw[i]
+            recs.append({"theta": int(r[0]), "q": int(r[1]), "extracted": int(r[2]), "edges": int(r[3]),
+                         "successes": int(r[4]), "flags": int(r[5]) & 0xFFFFFFFF, "samples": int(r[5]) >> 32})
+        stats["trace"] = recs
+    return out, stats
+
+
+def to_numpy_u64(t) -> np.ndarray:
+    """Copy a dist tensor to host as uint64."""
+    return t.detach().cpu().numpy().view(np.uint64)

@@ -1,0 +1,162 @@
+"""ctypes binding of libsssp.so (include/sssp.h), same names as the C ABI.
+
+Argument marshalling only: every step of the shortest-path computation runs
+in the library's HIP kernels. If the library is missing this module raises;
+there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_REPO = os.path.dirname(_HERE)
+LIB_PATH = os.path.join(_HERE, "libsssp.so")
+SOURCES = [os.path.join(_HERE, "csrc", "stepping.hip")]
+HEADER = os.path.join(_REPO, "include", "sssp.h")
+
+HIPCC_FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+# Status codes (sssp_status)
+SSSP_OK = 0
+SSSP_ERR_INVALID_ARGUMENT = 1
+SSSP_ERR_INVALID_GRAPH = 2
+SSSP_ERR_OUT_OF_MEMORY = 3
+SSSP_ERR_NO_DEVICE = 4
+SSSP_ERR_DEVICE = 5
+SSSP_ERR_STEP_LIMIT = 6
+SSSP_ERR_UNSUPPORTED = 7
+
+# Rules (sssp_rule)
+SSSP_RULE_RHO = 0
+SSSP_RULE_DELTA_STAR = 1
+SSSP_RULE_BF = 2
+SSSP_RULE_MIN = 3
+
+SSSP_OFFSETS_I32 = 0
+SSSP_OFFSETS_I64 = 1
+
+SSSP_INPUT_HOST = 0x1
+SSSP_INPUT_DEVICE = 0x2
+SSSP_TRUST_INPUT = 0x4
+
+
+class sssp_tuning(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", ctypes.c_uint32), ("hub_degree", ctypes.c_uint32),
+                ("chunk_edges", ctypes.c_uint32), ("list_divisor", ctypes.c_uint32),
+                ("sample_cap", ctypes.c_uint32), ("probe_cap", ctypes.c_uint32),
+                ("no_filter", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class sssp_step_record(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_uint64), ("q", ctypes.c_uint64), ("extracted", ctypes.c_uint64),
+                ("edges", ctypes.c_uint64), ("successes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("samples", ctypes.c_uint32)]
+
+
+class sssp_params(ctypes.Structure):
+    _fields_ = [("rule", ctypes.c_uint32), ("reserved0", ctypes.c_uint32), ("rho", ctypes.c_uint64),
+                ("delta", ctypes.c_uint64), ("seed", ctypes.c_uint64), ("max_steps", ctypes.c_uint64),
+                ("tuning", ctypes.POINTER(sssp_tuning)), ("extract_counts", ctypes.c_void_p),
+                ("trace", ctypes.c_void_p), ("trace_capacity", ctypes.c_uint64)]
+
+
+class sssp_stats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_uint64), ("extracted", ctypes.c_uint64), ("edges_relaxed", ctypes.c_uint64),
+                ("writemin_success", ctypes.c_uint64), ("dense_steps", ctypes.c_uint64),
+                ("sampled_steps", ctypes.c_uint64), ("device_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def build(force: bool = True) -> str:
+    """Compile libsssp.so for gfx950 with hipcc (in-tree)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["hipcc", *HIPCC_FLAGS, *SOURCES, "-o", tmp])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    """Load libsssp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no fallback path)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.sssp_default_params.argtypes = [ctypes.POINTER(sssp_params)]
+        L.sssp_default_params.restype = None
+        L.sssp_graph_create.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int, vp, vp, vp, ctypes.c_uint32,
+                                        vp, ctypes.POINTER(vp)]
+        L.sssp_graph_create.restype = ctypes.c_int
+        L.sssp_graph_destroy.argtypes = [vp]
+        L.sssp_graph_destroy.restype = ctypes.c_int
+        L.sssp_graph_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_uint64)]
+        L.sssp_graph_info.restype = ctypes.c_int
+        L.sssp_solve.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(sssp_params), vp, vp,
+                                 ctypes.POINTER(sssp_stats)]
+        L.sssp_solve.restype = ctypes.c_int
+        L.sssp_status_string.argtypes = [ctypes.c_int]
+        L.sssp_status_string.restype = ctypes.c_char_p
+        L.sssp_last_error.argtypes = []
+        L.sssp_last_error.restype = ctypes.c_char_p
+        L.sssp_abi_version.argtypes = []
+        L.sssp_abi_version.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+# Same-named thin wrappers over the C entry points.
+
+def sssp_default_params() -> sssp_params:
+    p = sssp_params()
+    lib().sssp_default_params(ctypes.byref(p))
+    return p
+
+
+def sssp_graph_create(n, m, ow, offsets_ptr, targets_ptr, weights_ptr, flags, stream_ptr):
+    """Returns (status, handle or None)."""
+    h = ctypes.c_void_p()
+    rc = lib().sssp_graph_create(int(n), int(m), int(ow), offsets_ptr, targets_ptr, weights_ptr, int(flags),
+                                 stream_ptr, ctypes.byref(h))
+    return rc, (h if rc == SSSP_OK else None)
+
+
+def sssp_graph_destroy(handle) -> int:
+    return lib().sssp_graph_destroy(handle)
+
+
+def sssp_graph_info(handle):
+    n = ctypes.c_int64()
+    m = ctypes.c_int64()
+    b = ctypes.c_uint64()
+    rc = lib().sssp_graph_info(handle, ctypes.byref(n), ctypes.byref(m), ctypes.byref(b))
+    return rc, n.value, m.value, b.value
+
+
+def sssp_solve(handle, sources_ptr, n_src, params: sssp_params, dist_ptr, stream_ptr, stats: sssp_stats | None):
+    return lib().sssp_solve(handle, sources_ptr, int(n_src), ctypes.byref(params) if params is not None else None,
+                            dist_ptr, stream_ptr, ctypes.byref(stats) if stats is not None else None)
+
+
+def sssp_status_string(s: int) -> str:
+    return lib().sssp_status_string(int(s)).decode()
+
+
+def sssp_last_error() -> str:
+    return lib().sssp_last_error().decode()
+
+
+def sssp_abi_version() -> int:
+    return lib().sssp_abi_version()

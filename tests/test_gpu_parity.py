@@ -1,0 +1,338 @@
+"""Parity of the HIP stepping loop with the CPU oracle, through the C ABI.
+
+Distances are integers, so the bar is bit-exact equality with the oracle's
+Dijkstra on the same seeded graph, for every rule and parameter (all stepping
+rules reach the same array: Sec. 3.2 and Table 2). Step-level properties are
+checked where the paper fixes them: the theta = min rule's exact step count,
+Lemma 5.1's extraction bound, Bellman-Ford's k_n + 1 steps and Thm. 5.5's
+Delta* step bound.
+"""
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+INF = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+@pytest.fixture(scope="module")
+def sp(torch_cuda):
+    import paper_2105_06145_amd as sp
+    return sp
+
+
+def run(sp, g, sources, **kw):
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+    try:
+        dist, st = sp.solve(G, sources, **kw)
+        return sp.to_numpy_u64(dist), st
+    finally:
+        G.close()
+
+
+def ref(g, s):
+    return oracle.dijkstra(g.offsets, g.targets, g.weights, int(s))
+
+
+def assert_same(got, exp, what=""):
+    if not np.array_equal(got, exp):
+        bad = np.flatnonzero(got != exp)
+        v = int(bad[0])
+        raise AssertionError(f"{what}: {bad.size} vertices differ; first {v}: gpu {int(got[v])} oracle {int(exp[v])}")
+
+
+RULES = [("rho", {"rho": 1}), ("rho", {"rho": 3}), ("rho", {"rho": 64}), ("rho", {"rho": 1 << 30}),
+         ("delta", {"delta": 1}), ("delta", {"delta": 777}), ("delta", {"delta": 1 << 40}), ("bf", {}),
+         ("min", {})]
+
+
+def tiny_graph(rng):
+    n = int(rng.integers(1, 130))
+    m = int(rng.integers(0, 5 * n + 1))
+    src = rng.integers(0, n, m)
+    dst = rng.integers(0, n, m)
+    wmax = int(rng.choice([1, 5, 1000, 2**32 - 1]))
+    w = rng.integers(1, wmax + 1, m, dtype=np.int64)
+    w[rng.random(m) < 0.1] = 0
+    return graphgen.from_arcs(n, src, dst, w)
+
+
+def test_tiny_random_graphs_all_rules(sp):
+    rng = np.random.default_rng(2024)
+    for i in range(120):
+        g = tiny_graph(rng)
+        s = int(rng.integers(0, g.n))
+        exp = ref(g, s)
+        G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+        for rule, kw in RULES:
+            dist, _ = sp.solve(G, [s], rule=rule, seed=i, **kw)
+            assert_same(sp.to_numpy_u64(dist)[0], exp, f"graph {i} n={g.n} m={g.m} rule {rule} {kw}")
+        G.close()
+
+
+def test_grid256_rho4096(sp):
+    w = graphgen.workload("grid256")
+    g = w.graph
+    got, st = run(sp, g, w.sources[:1], rule="rho", rho=4096)
+    exp = ref(g, w.sources[0])
+    assert_same(got[0], exp, "grid256 rho=4096")
+    assert oracle.certificate(g.offsets, g.targets, g.weights, int(w.sources[0]), got[0]) == (0, -1)
+    assert st["steps"] > 1 and st["edges_relaxed"] >= g.m
+
+
+def test_theta_min_exact_loop_counts(sp):
+    # w >= 1: each step extracts exactly the queue minimum's ties, all final.
+    g = graphgen.grid2d(96, 80, 1, 40, seed=5)
+    for s in (0, 4000):
+        exp = ref(g, s)
+        got, st = run(sp, g, [s], rule="min")
+        assert_same(got[0], exp, "min rule")
+        assert st["steps"] == oracle.distinct_finite(exp)
+        assert st["extracted"] == int((exp != INF).sum())
+        assert st["edges_relaxed"] == oracle.reachable_arcs(g.offsets, exp)
+
+
+def test_extraction_bound_lemma_5_1(sp):
+    # Positive weights: vertex v is extracted at most max(1, hop[v]) times.
+    g = graphgen.road(120, 120, seed=8)
+    s = int(graphgen.pick_sources(g.n, 1, 9, graphgen.largest_component(g))[0])
+    exp = ref(g, s)
+    hop, kn = oracle.hop_depth(g.offsets, g.targets, g.weights, s, exp)
+    bound = np.maximum(hop, 1)
+    bound[hop < 0] = 0
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+    for rule, kw in [("rho", {"rho": 512}), ("delta", {"delta": 4000}), ("bf", {})]:
+        dist, st = sp.solve(G, [s], rule=rule, extract_counts=True, **kw)
+        assert_same(sp.to_numpy_u64(dist)[0], exp, rule)
+        cnt = st["extract_counts"].cpu().numpy()[0]
+        assert np.all(cnt <= bound), (rule, int(np.argmax(cnt - bound)))
+        assert np.all(cnt[hop >= 0] >= 1)
+        assert int(cnt.sum()) == st["extracted"]
+    G.close()
+
+
+def test_step_bounds_bf_and_delta_star(sp):
+    g = graphgen.road(150, 150, seed=10)
+    s = int(graphgen.pick_sources(g.n, 1, 11, graphgen.largest_component(g))[0])
+    exp = ref(g, s)
+    _, kn = oracle.hop_depth(g.offsets, g.targets, g.weights, s, exp)
+    L = int(g.weights.max())
+    got, st = run(sp, g, [s], rule="bf")
+    assert_same(got[0], exp, "bf")
+    assert st["steps"] <= kn + 1
+    for delta in (1 << 10, 1 << 13, 1 << 16):
+        got, st = run(sp, g, [s], rule="delta", delta=delta)
+        assert_same(got[0], exp, f"delta {delta}")
+        assert st["steps"] <= -(-kn * L // delta) + kn + 1
+
+
+def test_rho_small_queue_extracts_everything(sp):
+    g = graphgen.rmat(13, 8, seed=12)
+    s = int(np.argmax(g.degrees()))
+    exp = ref(g, s)
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+    for rho in (16, 300, 5000):
+        dist, st = sp.solve(G, [s], rule="rho", rho=rho, trace=4096)
+        assert_same(sp.to_numpy_u64(dist)[0], exp, f"rho {rho}")
+        recs = st["trace"]
+        assert len(recs) == st["steps"]
+        dense_seen = 0
+        for r in recs:
+            rho_eff = max(1, rho // 10) if (r["flags"] & 1) and dense_seen < 2 else rho
+            if r["flags"] & 1:
+                dense_seen += 1
+            if r["q"] <= rho_eff:
+                assert r["extracted"] == r["q"] and not (r["flags"] & 4)
+            else:
+                assert r["flags"] & 4 and r["samples"] > 0
+                assert 1 <= r["extracted"] <= r["q"]
+        assert sum(r["extracted"] for r in recs) == st["extracted"]
+        assert sum(r["edges"] for r in recs) == st["edges_relaxed"]
+    G.close()
+
+
+@pytest.mark.parametrize("name", ["rmat16", "road300", "knn30"])
+def test_medium_workloads_every_rule(sp, name):
+    if name == "knn30":
+        g = graphgen.knn(30, 400, 0.01, 10, 1e6, seed=4001)
+        srcs = graphgen.pick_sources(g.n, 2, 4003)
+    else:
+        w = graphgen.workload(name, sources=2)
+        g, srcs = w.graph, w.sources
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+    for s in srcs:
+        exp = ref(g, s)
+        for rule, kw in [("rho", {"rho": 1 << 8}), ("rho", {"rho": 1 << 14}), ("delta", {"delta": 1 << 12}),
+                         ("delta", {"delta": 1 << 17}), ("bf", {})]:
+            dist, _ = sp.solve(G, [s], rule=rule, **kw)
+            assert_same(sp.to_numpy_u64(dist)[0], exp, f"{name} src {s} {rule} {kw}")
+    G.close()
+
+
+def test_tuning_variants_do_not_change_distances(sp):
+    g = graphgen.rmat(15, 16, seed=14)
+    s = int(np.argmax(g.degrees()))
+    exp = ref(g, s)
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+    variants = [dict(hub_degree=1, chunk_edges=64), dict(hub_degree=64, chunk_edges=64),
+                dict(list_divisor=0xFFFFFFFF), dict(list_divisor=1), dict(no_filter=1), dict(blocks_per_cu=1),
+                dict(sample_cap=16, probe_cap=16), dict(hub_degree=1 << 20)]
+    for tv in variants:
+        for rule, kw in [("rho", {"rho": 2048}), ("bf", {})]:
+            dist, _ = sp.solve(G, [s], rule=rule, tuning=tv, **kw)
+            assert_same(sp.to_numpy_u64(dist)[0], exp, f"tuning {tv} {rule}")
+    G.close()
+
+
+def test_seeds_and_repeats_agree(sp):
+    g = graphgen.rmat(14, 16, seed=15)
+    s = int(np.argmax(g.degrees()))
+    exp = ref(g, s)
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+    for seed in range(8):
+        dist, _ = sp.solve(G, [s], rule="rho", rho=500, seed=seed)
+        assert_same(sp.to_numpy_u64(dist)[0], exp, f"seed {seed}")
+    G.close()
+
+
+def test_edge_cases(sp):
+    # single vertex, no arcs
+    g = graphgen.from_arcs(1, [], [], [])
+    got, st = run(sp, g, [0])
+    assert got.tolist() == [[0]] and st["steps"] == 1
+    # isolated source in a bigger graph
+    g = graphgen.from_arcs(200, [1, 2], [2, 3], [4, 5])
+    got, _ = run(sp, g, [0], rule="bf")
+    assert got[0][0] == 0 and np.all(got[0][1:] == INF)
+    # self-loops and parallel arcs only
+    g = graphgen.from_arcs(3, [0, 0, 0, 1, 1], [0, 1, 1, 1, 2], [0, 9, 4, 1, 0])
+    for rule, kw in RULES:
+        got, _ = run(sp, g, [0], rule=rule, **kw)
+        assert got[0].tolist() == [0, 4, 4]
+    # distances beyond 2^32: a 300-arc path of maximal weights
+    n = 301
+    g = graphgen.from_arcs(n, np.arange(300), np.arange(1, 301), np.full(300, 2**32 - 1))
+    got, _ = run(sp, g, [0], rule="rho", rho=7)
+    assert_same(got[0], (np.arange(n, dtype=np.uint64) * np.uint64(2**32 - 1)), "max weights")
+    # vertex counts around a bitmap word boundary
+    for n in (63, 64, 65, 127, 128, 129):
+        rng = np.random.default_rng(n)
+        g = graphgen.from_arcs(n, rng.integers(0, n, 4 * n), rng.integers(0, n, 4 * n),
+                               rng.integers(0, 100, 4 * n))
+        got, _ = run(sp, g, [n - 1], rule="rho", rho=5)
+        assert_same(got[0], ref(g, n - 1), f"n={n}")
+
+
+def test_multiple_sources_rows(sp):
+    g = graphgen.road(80, 80, seed=16)
+    srcs = [0, 17, 5000, 6399, 17]
+    got, st = run(sp, g, srcs, rule="delta", delta=3000)
+    assert got.shape == (5, g.n)
+    for i, s in enumerate(srcs):
+        assert_same(got[i], ref(g, s), f"row {i}")
+
+
+def test_int32_offsets_and_device_input(sp, torch_cuda):
+    torch = torch_cuda
+    g = graphgen.rmat(12, 16, seed=17)
+    s = int(np.argmax(g.degrees()))
+    exp = ref(g, s)
+    G = sp.Graph.from_csr(g.offsets.astype(np.int32), g.targets, g.weights)
+    dist, _ = sp.solve(G, [s], rule="rho", rho=256)
+    assert_same(sp.to_numpy_u64(dist)[0], exp, "int32 offsets")
+    G.close()
+    off = torch.from_numpy(g.offsets).cuda()
+    tgt = torch.from_numpy(g.targets).cuda()
+    w = torch.from_numpy(g.weights.view(np.int32)).cuda()
+    G = sp.Graph.from_csr(off, tgt, w)
+    dist, _ = sp.solve(G, [s], rule="bf")
+    assert_same(sp.to_numpy_u64(dist)[0], exp, "device input")
+    G.close()
+    G = sp.Graph.from_csr(off.to(torch.int32), tgt, w)
+    dist, _ = sp.solve(G, [s], rule="delta", delta=5000)
+    assert_same(sp.to_numpy_u64(dist)[0], exp, "device input int32 offsets")
+    G.close()
+
+
+def test_device_validation_rejects_bad_graph(sp, torch_cuda):
+    torch = torch_cuda
+    off = torch.tensor([0, 2, 3, 3], dtype=torch.int64, device="cuda")
+    tgt = torch.tensor([1, 7, 0], dtype=torch.int32, device="cuda")  # 7 >= n
+    w = torch.ones(3, dtype=torch.int32, device="cuda")
+    with pytest.raises(sp.SSSPError) as ei:
+        sp.Graph.from_csr(off, tgt, w)
+    assert ei.value.status == 2 and "index 1" in str(ei.value)
+    off2 = torch.tensor([0, 2, 1, 3], dtype=torch.int64, device="cuda")
+    with pytest.raises(sp.SSSPError):
+        sp.Graph.from_csr(off2, torch.tensor([1, 2, 0], dtype=torch.int32, device="cuda"), w)
+
+
+def test_step_limit_and_bad_params(sp):
+    g = graphgen.from_arcs(50, np.arange(49), np.arange(1, 50), np.ones(49))
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+    with pytest.raises(sp.SSSPError) as ei:
+        sp.solve(G, [0], rule="bf", max_steps=5)
+    assert ei.value.status == 6
+    dist, st = sp.solve(G, [0], rule="bf", max_steps=50)
+    assert st["steps"] == 50  # 49 steps settle the path, one more empties Q
+    for bad in (dict(rule="rho", rho=0), dict(rule="delta", delta=0)):
+        with pytest.raises(sp.SSSPError) as ei:
+            sp.solve(G, [0], **bad)
+        assert ei.value.status == 1
+    with pytest.raises(sp.SSSPError):
+        sp.solve(G, [50])
+    G.close()
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads (the configurations the benchmark times).
+
+@pytest.fixture(scope="module")
+def rmat24():
+    return graphgen.workload("rmat24", sources=2)
+
+
+@pytest.fixture(scope="module")
+def road5000():
+    return graphgen.workload("road5000", sources=1)
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_full_rmat24_rho_sweep(sp, rmat24):
+    g = rmat24.graph
+    s = int(rmat24.sources[0])
+    exp = ref(g, s)
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+    for rho in (1 << 16, 1 << 20, 1 << 22):
+        dist, st = sp.solve(G, [s], rule="rho", rho=rho)
+        got = sp.to_numpy_u64(dist)[0]
+        assert_same(got, exp, f"rmat24 rho=2^{rho.bit_length() - 1}")
+        print(f"rmat24 rho={rho} steps={st['steps']} edges={st['edges_relaxed']} ms={st['device_ms']:.2f}",
+              flush=True)
+    assert oracle.certificate(g.offsets, g.targets, g.weights, s, got) == (0, -1)
+    # second source: certificate only (linear time)
+    s2 = int(rmat24.sources[1])
+    dist, _ = sp.solve(G, [s2], rule="rho", rho=1 << 20)
+    assert oracle.certificate(g.offsets, g.targets, g.weights, s2, sp.to_numpy_u64(dist)[0]) == (0, -1)
+    G.close()
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_full_road5000_delta_star_and_bf(sp, road5000):
+    g = road5000.graph
+    s = int(road5000.sources[0])
+    exp = ref(g, s)
+    G = sp.Graph.from_csr(g.offsets.astype(np.int32), g.targets, g.weights)
+    for rule, kw in [("delta", {"delta": 1 << 10}), ("delta", {"delta": 1 << 13}), ("delta", {"delta": 1 << 16}),
+                     ("bf", {})]:
+        dist, st = sp.solve(G, [s], rule=rule, **kw)
+        got = sp.to_numpy_u64(dist)[0]
+        assert_same(got, exp, f"road5000 {rule} {kw}")
+        print(f"road5000 {rule} {kw} steps={st['steps']} ms={st['device_ms']:.1f}", flush=True)
+    G.close()
