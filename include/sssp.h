@@ -138,6 +138,10 @@ typedef struct {
   uint64_t dense_steps;      /* steps whose Extract scanned the bitmap */
   uint64_t sampled_steps;    /* rho steps whose threshold came from sampling */
   double device_ms;          /* GPU time of the solve kernels, HIP events */
+  /* Wall-clock split of device_ms by phase, measured between consecutive
+   * grid barriers: [0] init (S0), [1] threshold sampling (S1, rho rule),
+   * [2] Extract (S2), [3] Relax + Update (S3, S4). */
+  double phase_ms[4];
 } sssp_stats;
 
 typedef struct sssp_graph sssp_graph; /* opaque */

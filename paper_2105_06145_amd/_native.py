@@ -67,10 +67,13 @@ class sssp_params(ctypes.Structure):
 class sssp_stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_uint64), ("extracted", ctypes.c_uint64), ("edges_relaxed", ctypes.c_uint64),
                 ("writemin_success", ctypes.c_uint64), ("dense_steps", ctypes.c_uint64),
-                ("sampled_steps", ctypes.c_uint64), ("device_ms", ctypes.c_double)]
+                ("sampled_steps", ctypes.c_uint64), ("device_ms", ctypes.c_double),
+                ("phase_ms", ctypes.c_double * 4)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["phase_ms"] = list(self.phase_ms)
+        return d
 
 
 def build(force: bool = True) -> str:

@@ -73,6 +73,7 @@ struct Control {
   unsigned status;  // 0 ok, 1 step limit, 2 barrier timeout
   ull theta;
   ull st_steps, st_extracted, st_edges, st_success, st_dense, st_sampled;
+  ull phase_ticks[4];  // init, threshold, extract, relax (workgroup 0's view)
   alignas(128) StepSlot slot[3];
 };
 
@@ -414,6 +415,14 @@ __global__ __launch_bounds__(WG) void stepping_kernel(KArgs a) {
   const ull n = (ull)a.n;
   Control* ctl = a.ctl;
   ull epoch = 0;
+  // Phase clock: workgroup 0 reads the wall clock as it leaves each barrier.
+  ull ph[4] = {0, 0, 0, 0};
+  long long tmark = wall_clock64();
+  auto phase_end = [&](int k) {
+    const long long now = wall_clock64();
+    ph[k] += (ull)(now - tmark);
+    tmark = now;
+  };
 
   // S0: delta = inf, Q empty; then delta[s] = 0 and Update(s).
   for (ull i = gtid; i < n; i += nthreads) a.dist[i] = INF;
@@ -428,6 +437,7 @@ __global__ __launch_bounds__(WG) void stepping_kernel(KArgs a) {
       }
     };
     if (!grid_sync(a, sh, epoch, seed_source)) return;
+    phase_end(0);
   }
 
   ull q = 1, minq = 0, idelta = 0, dense_steps = 0;
@@ -508,6 +518,7 @@ __global__ __launch_bounds__(WG) void stepping_kernel(KArgs a) {
           if (threadIdx.x == 0) ctl->theta = th;
         };
         if (!grid_sync(a, sh, epoch, choose)) return;
+        phase_end(1);
         theta = ld_agent(&ctl->theta);
       }
     }
@@ -569,6 +580,7 @@ __global__ __launch_bounds__(WG) void stepping_kernel(KArgs a) {
       }
     }
     if (!grid_sync(a, sh, epoch, NoSerial{})) return;
+    phase_end(2);
 
     // ---- S3/S4: Relax + Update ----
     {
@@ -696,6 +708,7 @@ __global__ __launch_bounds__(WG) void stepping_kernel(KArgs a) {
       }
     };
     if (!grid_sync(a, sh, epoch, bookkeeping)) return;
+    phase_end(3);
 
     // ---- S5: next queue state, identical in every workgroup ----
     const ull X = ld_agent(&S->f_count) + ld_agent(&S->hub_vertices);
@@ -704,6 +717,8 @@ __global__ __launch_bounds__(WG) void stepping_kernel(KArgs a) {
     list_valid = emit;
     if (dense) ++dense_steps;
   }
+  if (blockIdx.x == 0 && tid == 0)
+    for (int k = 0; k < 4; ++k) ctl->phase_ticks[k] = ph[k];
 }
 
 // Zero the control block before a solve (a kernel rather than a memset, so
@@ -1160,6 +1175,7 @@ sssp_status sssp_solve(const sssp_graph* gc, const int32_t* sources, int32_t n_s
       stats->writemin_success += hc.st_success;
       stats->dense_steps += hc.st_dense;
       stats->sampled_steps += hc.st_sampled;
+      for (int k = 0; k < 4; ++k) stats->phase_ms[k] += (double)hc.phase_ticks[k] / (double)g->tick_khz;
     }
   }
   (void)hipEventDestroy(ev0);
