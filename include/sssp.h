@@ -82,6 +82,9 @@ typedef enum { SSSP_OFFSETS_I32 = 0, SSSP_OFFSETS_I64 = 1 } sssp_offset_width;
 #define SSSP_INPUT_HOST 0x1u   /* offsets/targets/weights are host pointers */
 #define SSSP_INPUT_DEVICE 0x2u /* offsets/targets/weights are device pointers */
 #define SSSP_TRUST_INPUT 0x4u  /* skip CSR validation (caller guarantees it) */
+#define SSSP_KEEP_ORDER 0x8u   /* keep the caller's vertex numbering internally (by default the
+                                  library renumbers vertices by decreasing out-degree for cache
+                                  locality; results are always in the caller's ids) */
 
 /* Tuning knobs. Zero in any field selects the library default. None of them
  * changes the distances; they change speed, steps and work only. */
@@ -142,6 +145,9 @@ typedef struct {
    * grid barriers: [0] init (S0), [1] threshold sampling (S1, rho rule),
    * [2] Extract (S2), [3] Relax + Update (S3, S4). */
   double phase_ms[4];
+  /* Relax load balance, summed over steps: [0] the slowest workgroup's
+   * Relax time, [1] the mean workgroup's Relax time. */
+  double relax_wg_ms[2];
 } sssp_stats;
 
 typedef struct sssp_graph sssp_graph; /* opaque */

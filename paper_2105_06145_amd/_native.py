@@ -14,7 +14,7 @@ import subprocess
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _REPO = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libsssp.so")
-SOURCES = [os.path.join(_HERE, "csrc", "stepping.hip")]
+SOURCES = [os.path.join(_HERE, "csrc", "stepping.hip"), os.path.join(_HERE, "csrc", "graph.hip")]
 HEADER = os.path.join(_REPO, "include", "sssp.h")
 
 HIPCC_FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
@@ -42,6 +42,7 @@ SSSP_OFFSETS_I64 = 1
 SSSP_INPUT_HOST = 0x1
 SSSP_INPUT_DEVICE = 0x2
 SSSP_TRUST_INPUT = 0x4
+SSSP_KEEP_ORDER = 0x8
 
 
 class sssp_tuning(ctypes.Structure):
@@ -68,11 +69,12 @@ class sssp_stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_uint64), ("extracted", ctypes.c_uint64), ("edges_relaxed", ctypes.c_uint64),
                 ("writemin_success", ctypes.c_uint64), ("dense_steps", ctypes.c_uint64),
                 ("sampled_steps", ctypes.c_uint64), ("device_ms", ctypes.c_double),
-                ("phase_ms", ctypes.c_double * 4)]
+                ("phase_ms", ctypes.c_double * 4), ("relax_wg_ms", ctypes.c_double * 2)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["phase_ms"] = list(self.phase_ms)
+        d["relax_wg_ms"] = list(self.relax_wg_ms)
         return d
 
 

@@ -1,0 +1,96 @@
+// Host-side definitions shared by the library's translation units
+// (graph.hip: graph creation; stepping.hip: the solve).
+#ifndef SSSP_INTERNAL_H
+#define SSSP_INTERNAL_H
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/sssp.h"
+
+namespace sssp_impl {
+
+typedef unsigned long long ull;
+constexpr ull INF = ~0ull;
+
+// Thread-local detail string behind sssp_last_error().
+std::string& last_error();
+
+inline sssp_status fail(sssp_status s, const std::string& msg) {
+  last_error() = msg;
+  return s;
+}
+
+inline sssp_status from_hip(hipError_t e) {
+  return e == hipErrorOutOfMemory ? SSSP_ERR_OUT_OF_MEMORY : SSSP_ERR_DEVICE;
+}
+
+#define SSSP_HIP_TRY(expr)                                                                   \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return ::sssp_impl::fail(::sssp_impl::from_hip(e_),                                    \
+                               std::string(#expr) + ": " + hipGetErrorString(e_));           \
+  } while (0)
+
+// Owned device allocation.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t alloc(size_t b) {
+    release();
+    bytes = b;
+    return hipMalloc(&p, b ? b : 8);
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+}  // namespace sssp_impl
+
+// The opaque graph handle: the device copy of the graph in the library's own
+// layout, plus the solve workspace (allocated on first solve).
+struct sssp_graph {
+  int device = 0;
+  int64_t n = 0, m = 0;
+  int cus = 0;
+  uint64_t tick_khz = 100000;  // wall-clock counter rate
+  // Graph, in internal vertex ids. When `relabelled`, internal id i is the
+  // caller's vertex perm[i] and inv[v] is the internal id of caller vertex v.
+  sssp_impl::DevBuf off;    // int64[n + 1]
+  sssp_impl::DevBuf edges;  // uint64[m]: (weight << 32) | internal target
+  sssp_impl::DevBuf perm, inv;
+  bool relabelled = false;
+  // Workspace.
+  bool ws_ready = false;
+  uint32_t ws_hub_degree = 0, ws_chunk = 0, ws_probe_cap = 0, ws_G = 0;
+  sssp_impl::DevBuf dist_int, bitmap, hubmask, F, H, L0, L1, samples, parts, ctl, args;
+  void* hargs = nullptr;  // pinned staging copy of the kernel arguments
+
+  uint64_t graph_bytes() const { return off.bytes + edges.bytes + perm.bytes + inv.bytes; }
+  uint64_t workspace_bytes() const {
+    return dist_int.bytes + bitmap.bytes + hubmask.bytes + F.bytes + H.bytes + L0.bytes + L1.bytes +
+           samples.bytes + parts.bytes + ctl.bytes + args.bytes;
+  }
+  void release_ws() {
+    for (sssp_impl::DevBuf* b : {&dist_int, &bitmap, &hubmask, &F, &H, &L0, &L1, &samples, &parts, &ctl, &args})
+      b->release();
+    if (hargs) (void)hipHostFree(hargs);
+    hargs = nullptr;
+    ws_ready = false;
+  }
+  void release_all() {
+    release_ws();
+    off.release();
+    edges.release();
+    perm.release();
+    inv.release();
+  }
+};
+
+#endif  // SSSP_INTERNAL_H

@@ -186,6 +186,13 @@ def test_tuning_variants_do_not_change_distances(sp):
             dist, _ = sp.solve(G, [s], rule=rule, tuning=tv, **kw)
             assert_same(sp.to_numpy_u64(dist)[0], exp, f"tuning {tv} {rule}")
     G.close()
+    # The caller's vertex order kept internally (no degree renumbering).
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights, reorder=False)
+    for rule, kw in [("rho", {"rho": 2048}), ("delta", {"delta": 3000}), ("bf", {})]:
+        dist, st = sp.solve(G, [s], rule=rule, extract_counts=True, **kw)
+        assert_same(sp.to_numpy_u64(dist)[0], exp, f"keep order {rule}")
+        assert int(st["extract_counts"].sum()) == st["extracted"]
+    G.close()
 
 
 def test_seeds_and_repeats_agree(sp):
