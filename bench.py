@@ -30,7 +30,8 @@ sys.path.insert(0, REPO)
 
 METRIC = "edges relaxed/s (GTEPS) + % HBM roofline; p50/p99 query latency batched vs plain"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(REPO, "paper_2105_06145_amd", "csrc", "stepping.hip")
+KERNEL_SRCS = [os.path.join(REPO, "paper_2105_06145_amd", "csrc", f)
+               for f in ("stepping.hip", "graph.hip", "internal.h")]
 TRAFFIC_FILE = os.path.join(REPO, "profiles", "traffic_stepping_kernel_rmat24.json")
 
 WORKLOADS = {
@@ -46,17 +47,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(n: int, trace: list, offset_bytes: int = 8) -> int:
+def algorithmic_bytes(n: int, trace: list, offset_bytes: int = 8, relabelled: bool = True) -> int:
     """Bytes the method must move for one solve, from the per-step trace.
 
     S0: 8n (distance fill) + n/8 (bitmap clear).
+    Output in caller ids (relabelled graph): 4n (id map) + 8n (read) + 8n (write).
     Extract, bitmap step: n/8 (flag scan) + 8 q (keys of members).
     Extract, list step:   12 q (list entry + key); + 4 per kept member.
     Per extracted vertex: 2 * offset_bytes (row bounds) + 8 (its key) + 8 (F write + read).
     Per relaxed arc:      8 (packed target, weight) + 8 (key of the target).
     Per successful WriteMin: 8 (key write) + 8 (flag word RMW) [+ 4 list append].
     """
-    b = 8 * n + n // 8
+    b = 8 * n + n // 8 + (20 * n if relabelled else 0)
     for i, r in enumerate(trace):
         dense = r["flags"] & 1
         emit = r["flags"] & 2
@@ -72,17 +74,23 @@ def algorithmic_bytes(n: int, trace: list, offset_bytes: int = 8) -> int:
 
 
 def kernel_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str):
+def load_traffic(workload: str, rho: int):
+    """HBM bytes per launch from the committed rocprofv3 counters, or None when
+    they were taken on other kernel sources, another workload or another rho."""
     try:
         d = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     if d.get("kernel_sha") != kernel_sha() or d.get("workload") != workload:
         return None
-    return d.get("traffic_bytes_per_launch")
+    rec = d.get("by_rho", {}).get(str(rho))
+    return rec.get("traffic_bytes_per_launch") if rec else None
 
 
 def main():
@@ -91,13 +99,29 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
-    ap.add_argument("--rho", type=int, default=0, help="fixed rho (0 = pick the fastest of the sweep)")
+    ap.add_argument("--rho", type=int, default=1 << 18, help="rho for the timed solves")
     ap.add_argument("--delta", type=int, default=1 << 13)
-    ap.add_argument("--sweep", default="16,17,18,19,20,21,22", help="log2(rho) values tried before timing")
+    ap.add_argument("--sweep", default="", metavar="LOG2_LIST",
+                    help="e.g. 16,17,18,19,20,21,22: time 3 solves per rho first and use the fastest")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-settle-cap", type=int, default=0,
                     help="stop the CPU oracle after this many settled vertices (0 = full solve)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of this many MiB (5 times) and exit; "
+                         "used to scale the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        nbytes = args.copy_calibration << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 5}), flush=True)
+        return
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -125,10 +149,10 @@ def main():
     if rule == "rho":
         if args.workload == "grid256":
             choices = [4096]
-        elif args.rho:
-            choices = [args.rho]
-        else:
+        elif args.sweep:
             choices = [1 << int(x) for x in args.sweep.split(",") if x]
+        else:
+            choices = []
         for rho in choices:
             times = []
             for _ in range(3):
@@ -139,8 +163,7 @@ def main():
                           "gteps": st["edges_relaxed"] / (np.median(times) * 1e6)})
             log(f"  sweep rho=2^{rho.bit_length() - 1}: {np.median(times):.3f} ms, steps {st['steps']}, "
                 f"E_r {st['edges_relaxed']}")
-        best = min(sweep, key=lambda r: r["ms"])
-        fixed = {"rho": best["rho"]}
+        fixed = {"rho": min(sweep, key=lambda r: r["ms"])["rho"] if sweep else args.rho}
     else:
         fixed = {"delta": args.delta}
 
@@ -175,7 +198,7 @@ def main():
     b_alg = algorithmic_bytes(g.n, trace)
     kernel_avg_ms = kernel_ms / args.steps
     achieved = b_alg / (kernel_avg_ms * 1e-3) / 1e9
-    traffic = load_traffic(args.workload)
+    traffic = load_traffic(args.workload, fixed.get("rho", 0))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "stepping_kernel", "algorithmic_bytes_per_launch": int(b_alg),
