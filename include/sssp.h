@@ -99,7 +99,10 @@ typedef struct {
   uint32_t sample_cap;    /* maximum rho-stepping sample size */
   uint32_t probe_cap;     /* maximum bitmap probes per sampled step */
   uint32_t no_filter;     /* 1 = skip the read-before-atomic filter in Relax */
-  uint32_t reserved;
+  uint32_t teams;         /* independent solves in flight: the persistent grid is split into
+                             this many teams of workgroups, each solving one source at a time
+                             (must divide the grid size). 0 = 1 for a single source, else a
+                             power of two >= 8, about one team per source */
 } sssp_tuning;
 
 /* One record per step, written when params.trace is set. */
@@ -115,9 +118,18 @@ typedef struct {
   uint32_t samples;   /* sample size when bit 2 is set */
 } sssp_step_record;
 
+/* sssp_params.flags */
+#define SSSP_SOLVE_SNAPSHOT_KEYS 0x1u /* Relax each extracted vertex with the key it had when it was
+                                         extracted, instead of its current key (which another
+                                         relaxation of the same step may already have lowered).
+                                         Extraction sets, step counts and traces then do not depend
+                                         on the order in which concurrent WriteMins land, so runs
+                                         with the Delta*, Bellman-Ford and min rules repeat exactly;
+                                         usually more relaxations than the default. */
+
 typedef struct {
   uint32_t rule;      /* sssp_rule */
-  uint32_t reserved0;
+  uint32_t flags;     /* SSSP_SOLVE_* bits; others must be 0 */
   uint64_t rho;       /* SSSP_RULE_RHO: rho >= 1 */
   uint64_t delta;     /* SSSP_RULE_DELTA_STAR: Delta >= 1 */
   uint64_t seed;      /* sampling seed (rho rule); affects steps and work only */
@@ -141,13 +153,15 @@ typedef struct {
   uint64_t dense_steps;      /* steps whose Extract scanned the bitmap */
   uint64_t sampled_steps;    /* rho steps whose threshold came from sampling */
   double device_ms;          /* GPU time of the solve kernels, HIP events */
-  /* Wall-clock split of device_ms by phase, measured between consecutive
-   * grid barriers: [0] init (S0), [1] threshold sampling (S1, rho rule),
-   * [2] Extract (S2), [3] Relax + Update (S3, S4). */
+  /* Wall-clock split by phase, measured by the first team between its
+   * consecutive barriers (over all sources it solved): [0] init (S0),
+   * [1] threshold sampling (S1, rho rule), [2] Extract (S2), [3] Relax +
+   * Update (S3, S4). */
   double phase_ms[4];
-  /* Relax load balance, summed over steps: [0] the slowest workgroup's
-   * Relax time, [1] the mean workgroup's Relax time. */
+  /* Relax load balance in the first team, summed over its steps: [0] the
+   * slowest workgroup's Relax time, [1] the mean workgroup's Relax time. */
   double relax_wg_ms[2];
+  uint64_t teams;            /* teams the grid was split into */
 } sssp_stats;
 
 typedef struct sssp_graph sssp_graph; /* opaque */
@@ -187,7 +201,10 @@ sssp_status sssp_graph_destroy(sssp_graph* g);
 sssp_status sssp_graph_info(const sssp_graph* g, int64_t* n, int64_t* m, uint64_t* device_bytes);
 
 /*
- * Solve from each of n_src sources (Alg. 1 once per source).
+ * Solve from each of n_src sources (Alg. 1 once per source). All sources run
+ * in one persistent launch: its workgroups form tuning.teams teams, and each
+ * team takes the next unsolved source until none is left, so independent
+ * queries proceed side by side.
  *   sources  host array of n_src vertex ids in [0, n).
  *   params   rule and parameters (see sssp_params); NULL = defaults.
  *   dist     device pointer to n_src * n uint64 entries, row-major:

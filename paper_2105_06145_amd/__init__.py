@@ -125,11 +125,13 @@ def make_tuning(**kw) -> sssp_tuning:
 
 def solve(g: Graph, sources, rule: str = "rho", rho: int = 1 << 20, delta: int = 1 << 13, seed: int = 1,
           max_steps: int = 0, tuning: dict | sssp_tuning | None = None, out=None, stream=None,
-          trace: int = 0, extract_counts: bool = False):
+          trace: int = 0, extract_counts: bool = False, snapshot_keys: bool = False):
     """Solve from each source. Returns (dist, stats) where dist is a torch
     int64 CUDA tensor (n_src, n) holding uint64 bit patterns (-1 = unreachable)
     and stats is a dict; with trace > 0 stats["trace"] holds per-step records,
-    with extract_counts=True stats["extract_counts"] a (n_src, n) int32 tensor."""
+    with extract_counts=True stats["extract_counts"] a (n_src, n) int32 tensor.
+    snapshot_keys=True relaxes with the keys vertices were extracted with, which
+    makes extraction sets independent of WriteMin ordering."""
     torch = _torch()
     src = np.ascontiguousarray(np.atleast_1d(np.asarray(sources)), dtype=np.int32)
     ns = int(src.shape[0])
@@ -144,6 +146,7 @@ def solve(g: Graph, sources, rule: str = "rho", rho: int = 1 << 20, delta: int =
     p.delta = int(delta)
     p.seed = int(seed)
     p.max_steps = int(max_steps)
+    p.flags = N.SSSP_SOLVE_SNAPSHOT_KEYS if snapshot_keys else 0
     tun = None
     if tuning is not None:
         tun = tuning if isinstance(tuning, sssp_tuning) else make_tuning(**tuning)

@@ -43,13 +43,14 @@ SSSP_INPUT_HOST = 0x1
 SSSP_INPUT_DEVICE = 0x2
 SSSP_TRUST_INPUT = 0x4
 SSSP_KEEP_ORDER = 0x8
+SSSP_SOLVE_SNAPSHOT_KEYS = 0x1
 
 
 class sssp_tuning(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_uint32), ("hub_degree", ctypes.c_uint32),
                 ("chunk_edges", ctypes.c_uint32), ("list_divisor", ctypes.c_uint32),
                 ("sample_cap", ctypes.c_uint32), ("probe_cap", ctypes.c_uint32),
-                ("no_filter", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("no_filter", ctypes.c_uint32), ("teams", ctypes.c_uint32)]
 
 
 class sssp_step_record(ctypes.Structure):
@@ -59,7 +60,7 @@ class sssp_step_record(ctypes.Structure):
 
 
 class sssp_params(ctypes.Structure):
-    _fields_ = [("rule", ctypes.c_uint32), ("reserved0", ctypes.c_uint32), ("rho", ctypes.c_uint64),
+    _fields_ = [("rule", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("rho", ctypes.c_uint64),
                 ("delta", ctypes.c_uint64), ("seed", ctypes.c_uint64), ("max_steps", ctypes.c_uint64),
                 ("tuning", ctypes.POINTER(sssp_tuning)), ("extract_counts", ctypes.c_void_p),
                 ("trace", ctypes.c_void_p), ("trace_capacity", ctypes.c_uint64)]
@@ -69,7 +70,8 @@ class sssp_stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_uint64), ("extracted", ctypes.c_uint64), ("edges_relaxed", ctypes.c_uint64),
                 ("writemin_success", ctypes.c_uint64), ("dense_steps", ctypes.c_uint64),
                 ("sampled_steps", ctypes.c_uint64), ("device_ms", ctypes.c_double),
-                ("phase_ms", ctypes.c_double * 4), ("relax_wg_ms", ctypes.c_double * 2)]
+                ("phase_ms", ctypes.c_double * 4), ("relax_wg_ms", ctypes.c_double * 2),
+                ("teams", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}

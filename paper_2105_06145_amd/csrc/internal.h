@@ -68,21 +68,23 @@ struct sssp_graph {
   bool relabelled = false;
   // Workspace.
   bool ws_ready = false;
-  uint32_t ws_hub_degree = 0, ws_chunk = 0, ws_probe_cap = 0, ws_G = 0;
-  sssp_impl::DevBuf dist_int, bitmap, hubmask, F, H, L0, L1, samples, parts, ctl, args;
+  uint32_t ws_hub_degree = 0, ws_chunk = 0, ws_probe_cap = 0, ws_G = 0, ws_teams = 0;
+  uint64_t ws_src_cap = 0;  // sources the `srcs` buffer holds
+  sssp_impl::DevBuf dist_int, bitmap, hubmask, F, FD, H, L, samples, parts, ctl, args, srcs;
   void* hargs = nullptr;  // pinned staging copy of the kernel arguments
 
   uint64_t graph_bytes() const { return off.bytes + edges.bytes + perm.bytes + inv.bytes; }
   uint64_t workspace_bytes() const {
-    return dist_int.bytes + bitmap.bytes + hubmask.bytes + F.bytes + H.bytes + L0.bytes + L1.bytes +
-           samples.bytes + parts.bytes + ctl.bytes + args.bytes;
+    return dist_int.bytes + bitmap.bytes + hubmask.bytes + F.bytes + FD.bytes + H.bytes + L.bytes + samples.bytes +
+           parts.bytes + ctl.bytes + args.bytes + srcs.bytes;
   }
   void release_ws() {
-    for (sssp_impl::DevBuf* b : {&dist_int, &bitmap, &hubmask, &F, &H, &L0, &L1, &samples, &parts, &ctl, &args})
+    for (sssp_impl::DevBuf* b : {&dist_int, &bitmap, &hubmask, &F, &FD, &H, &L, &samples, &parts, &ctl, &args, &srcs})
       b->release();
     if (hargs) (void)hipHostFree(hargs);
     hargs = nullptr;
     ws_ready = false;
+    ws_src_cap = 0;
   }
   void release_all() {
     release_ws();

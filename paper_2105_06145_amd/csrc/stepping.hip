@@ -1,7 +1,7 @@
 // Persistent stepping-loop kernel for single-source shortest paths on
-// MI355X (gfx950), and the C ABI declared in include/sssp.h.
+// MI355X (gfx950), and sssp_solve of the C ABI (include/sssp.h).
 //
-// One cooperative launch runs Alg. 1 (Sec. 3.2) for one source:
+// One cooperative launch runs Alg. 1 (Sec. 3.2) for every requested source:
 //
 //   S0 init      delta[.] = inf, bitmap = 0; delta[s] = 0, Update(s).
 //   S1 ExtDist   theta per Table 2: rho-th smallest by sampling (Sec. 6,
@@ -12,30 +12,46 @@
 //                mode), so small steps do not scan all n flags.
 //   S3 Relax     for u in F, v in N(u): WriteMin(delta[v], delta[u] + w) as a
 //                64-bit atomic min (Sec. 2 WriteMin), skipped when a plain read
-//                of delta[v] already shows no improvement.
+//                of delta[v] already shows no improvement. delta[u] is read
+//                when u's arcs are relaxed, so a u whose key another WriteMin
+//                of the same step has lowered already propagates the lower key.
+//                With SSSP_SOLVE_SNAPSHOT_KEYS, delta[u] is instead the key u
+//                was extracted with (kept beside u in F): what a step extracts
+//                and which vertices it improves then do not depend on the order
+//                in which concurrent WriteMins land, so for a fixed theta
+//                sequence the run repeats exactly.
 //   S4 Update    a successful WriteMin sets v's flag with an atomic OR; the old
 //                word tells whether v is new to Q, so the explicit list gets
 //                each new member once, with no hash table or pack pass.
-//   S5 loop      until |Q| = 0. Phases are separated by grid barriers, so
-//                Extract never overlaps Update (Sec. 3.1).
+//   S5 loop      until |Q| = 0. Phases are separated by barriers, so Extract
+//                never overlaps Update (Sec. 3.1).
 //
-// Work distribution. Each workgroup owns a static slice of the queue: a
-// contiguous range of bitmap words (bitmap steps) or of the explicit list
-// (list steps). What it extracts goes to its own segment of F, so Extract
-// needs no shared counter; in Relax it processes its own segment in tiles of
-// 256 vertices, whose (row begin, delta) pairs and degree prefix sums sit in
-// LDS, so consecutive lanes read consecutive 8-byte (target, weight) arcs.
-// Vertices above hub_degree are cut into fixed-size edge chunks that all
-// workgroups share. Counters are per-workgroup partials, summed by the last
-// workgroup to reach the step's final barrier.
+// Teams. The grid is split into `nteams` teams; team t is the workgroups b
+// with b % nteams == t. Each team repeatedly takes the next unsolved source
+// and runs the loop above on it with its own queue state, so many small
+// queries proceed side by side in one launch (batched solves), while
+// nteams = 1 gives one whole-grid solve at a time. With nteams a multiple of
+// eight, every team sits on one XCD (workgroups are dealt to the eight XCDs
+// round-robin; the kernel checks this against the XCC_ID hardware register).
 //
-// Memory visibility across the eight XCDs (each with its own L2): the grid
-// barrier is hierarchical. Workgroups of one XCD (read from the XCC_ID
-// hardware register) meet first; the last of them writes back that XCD's L2
-// (agent-scope release) before arriving at the global counter, and after the
-// global release invalidates the XCD's L2 (agent-scope acquire) before
-// releasing its group. Data other workgroups wrote in earlier phases is read
-// with agent-scope loads, which bypass the per-CU L1.
+// Work distribution inside a team. Each workgroup owns a slice of the queue:
+// interleaved blocks of bitmap words (bitmap steps) or a contiguous slice of
+// the explicit list (list steps). What it extracts goes to its own segment
+// of F, so Extract needs no shared counter; in Relax it processes its own
+// segment in tiles of 256 vertices whose (row begin, delta) pairs and degree
+// prefix sums sit in LDS, so consecutive lanes read consecutive 8-byte
+// (target, weight) arcs. Vertices above hub_degree are cut into fixed-size
+// edge chunks shared by the team. Counters are per-workgroup partials, summed
+// by the last workgroup to reach the step's final barrier.
+//
+// Barriers and memory visibility across XCDs (each has its own L2). A
+// whole-grid team meets in two levels: the workgroups of one XCD (grouped by
+// XCC_ID) first; the last of them writes back that XCD's L2 (agent-scope
+// release) and arrives at the global counter; after the global release each
+// XCD leader invalidates (agent-scope acquire) and releases its group. A team
+// inside one XCD meets on a single counter whose last arriver does the same.
+// Data other workgroups wrote in earlier phases is read with agent-scope
+// loads, which bypass the per-CU L1. Every wait is bounded.
 
 #include <hip/hip_runtime.h>
 
@@ -49,26 +65,21 @@
 
 using namespace sssp_impl;
 
-// Marks device pointers that live in global memory. Expands to nothing: the
-// variant that spelled out the global address space here aborted on the GPU
-// with no diagnosed cause, so it stays switched off.
-#define GPTR
-
 namespace {
 
 constexpr int WG = 256;
 constexpr int WAVES = WG / 64;
-constexpr int UNROLL = 4;  // arcs / list entries per lane per iteration
-constexpr int BATCH = 4;   // queue members per lane per round in bitmap scans
+constexpr int UNROLL = 4;       // arcs / list entries per lane per iteration
+constexpr int BATCH = 4;        // queue members per lane per round in bitmap scans
 constexpr int MAX_XCC = 16;
 constexpr int BLOCK_WORDS = 4;  // bitmap words per ownership block (256 vertices)
 
 // ---------------------------------------------------------------------------
-// Device-side control block.
+// Control blocks.
 
 struct alignas(128) StepSlot {
   ull h_count;      // hub chunk tasks in H
-  ull list_next;    // entries written to the next explicit list
+  ull list_next;    // entries reserved in the next explicit list
   ull nsamples;     // accepted threshold samples
   ull x_total;      // vertices extracted (sum of partials)
   ull fresh_total;  // vertices whose flag went 0 -> 1 in Relax
@@ -83,28 +94,38 @@ struct alignas(128) Line {
   ull pad[15];
 };
 
-struct Control {
-  Line arrive_flat;  // first (flat) barrier
+// Per-team state.
+struct TeamCtl {
+  Line arrive;  // team barrier (teams inside one XCD)
+  Line gen;
+  alignas(128) ull theta;
+  ull query;   // index of the source being solved
+  ull status;  // 1: step limit reached on some query
+  ull st_steps, st_extracted, st_edges, st_success, st_dense, st_sampled;
+  ull relax_busy_max, relax_busy_sum;
+  ull phase_ticks[4];  // init, threshold, extract, relax (the team's first workgroup)
+  alignas(128) StepSlot slot[3];
+};
+
+// Whole-grid state.
+struct GridCtl {
+  Line arrive_flat;  // the first barrier
   Line gen_flat;
-  Line arrive;       // group leaders arriving at the global level
+  Line arrive;  // global level of the whole-grid barrier
   Line gen;
   Line grp_arrive[MAX_XCC];
   Line grp_gen[MAX_XCC];
   Line grp_size[MAX_XCC];
+  Line next_query;
+  Line mismatch;  // some workgroup is not on the XCD its index implies
   alignas(128) unsigned abort_flag;
-  unsigned status;  // 0 ok, 1 step limit
-  ull theta;
+  unsigned pad0;
   ull ngroups;
-  ull st_steps, st_extracted, st_edges, st_success, st_dense, st_sampled;
-  ull phase_ticks[4];  // init, threshold, extract, relax (workgroup 0's view)
-  ull relax_busy_max, relax_busy_sum;  // per step: slowest workgroup, sum over workgroups
-  alignas(128) StepSlot slot[3];
 };
 
-constexpr unsigned ST_OK = 0, ST_STEP_LIMIT = 1;
+constexpr unsigned ST_STEP_LIMIT = 1;
 
-// Per-workgroup partial counts of one step (written with plain stores, summed
-// by the last workgroup at the step's final barrier).
+// Per-workgroup partial counts of one step.
 struct alignas(64) Part {
   ull x;        // vertices extracted
   ull minkept;  // min key of members left in Q
@@ -119,35 +140,39 @@ struct alignas(64) Part {
 struct KArgs {
   int64_t n;
   uint64_t nwords;
-  const GPTR int64_t* off;
-  const GPTR ull* edges;    // (weight << 32) | target
-  const GPTR ull* hubmask;  // bit v set iff deg(v) > hub_degree
-  GPTR ull* dist;            // tentative distances, internal ids
-  GPTR ull* dist_out;        // the caller's row (caller ids) when the graph is relabelled
-  const GPTR int32_t* perm;  // internal id -> caller id (NULL: identity)
-  const GPTR int32_t* inv;   // caller id -> internal id (NULL: identity)
-  GPTR ull* bitmap;
-  GPTR int32_t* F;  // G segments of segcap entries
-  GPTR ull* H;      // (vertex << 32) | chunk index
-  GPTR int32_t* L0;
-  GPTR int32_t* L1;
-  GPTR ull* samples;
-  GPTR Part* parts;
-  GPTR Control* ctl;
-  GPTR uint32_t* xcount;
-  GPTR sssp_step_record* trace;
+  const int64_t* off;
+  const ull* edges;     // (weight << 32) | target
+  const ull* hubmask;   // bit v set iff deg(v) > hub_degree
+  const int32_t* perm;  // internal id -> caller id (NULL: identity)
+  const int32_t* inv;   // caller id -> internal id (NULL: identity)
+  const int32_t* srcs;  // n_src sources, caller ids
+  ull* dist_out;        // caller's rows, n_src x n, caller ids
+  ull* dist_int;        // per-team internal rows (relabelled graphs), else NULL
+  ull* bitmap;          // per team, nwords
+  int32_t* F;           // per workgroup, segcap: extracted vertices
+  ull* FD;              // per workgroup, segcap: their keys when extracted
+  ull* H;               // per team, hcap pairs: ((vertex << 32) | chunk index, key)
+  int32_t* L;           // per team, 2 x lcap
+  ull* samples;         // per team, probe_cap
+  Part* parts;          // per workgroup
+  TeamCtl* teams;
+  GridCtl* grid;
+  uint32_t* xcount;  // n_src x n (caller ids) or NULL
+  sssp_step_record* trace;
   uint64_t trace_cap;
   uint64_t rho, delta, seed, max_steps;
   uint64_t list_threshold;
   uint64_t tlimit;
-  uint64_t segcap;
-  int32_t source;
+  uint64_t segcap, hcap, lcap;
+  int64_t n_src;
   uint32_t rule;
-  uint32_t G;
+  uint32_t G;       // workgroups in the grid
+  uint32_t nteams;  // teams; team size T = G / nteams
   uint32_t chunk_edges;
   uint32_t sample_cap;
   uint32_t probe_cap;
   uint32_t filter;
+  uint32_t snapshot;  // relax with the keys at extraction
 };
 
 struct Shared {
@@ -162,13 +187,32 @@ struct Shared {
   int abort;
 };
 
-// Barrier bookkeeping kept in registers by every workgroup.
-struct Sync {
-  ull epoch = 0;
-  unsigned xcc = 0;
-  ull gsz = 1;
-  ull ngroups = 1;
+__shared__ Shared g_sh;
+
+// Everything a workgroup needs to know about its team, in registers.
+struct Team {
+  ull id, rank, T;  // team index, rank in the team, team size
+  TeamCtl* ctl;
+  ull* bitmap;
+  ull* H;
+  int32_t* L;
+  ull* samples;
+  int32_t* Fb;  // this workgroup's F segment: vertices
+  ull* FDb;     // and their keys at extraction
+  // barrier
+  ull epoch;
+  ull* l1_arrive;
+  ull* l1_gen;
+  ull l1_size;
+  ull* l2_arrive;  // NULL: single-level barrier
+  ull* l2_gen;
+  ull l2_size;
+  bool member_release;  // every member releases at agent scope
 };
+
+// LDS copy of the workgroup's Team for the out-of-line phase functions (a
+// reference to a kernel local would place it in scratch memory).
+__shared__ Team g_tm;
 
 // ---------------------------------------------------------------------------
 // Small device helpers.
@@ -295,22 +339,22 @@ __device__ void wg_reduce4(Shared& sh, ull& a, ull& b, ull& c, ull& mn) {
 }
 
 // ---------------------------------------------------------------------------
-// Grid barriers. Every workgroup calls them in the same order. The last
-// workgroup to arrive runs `serial` (whole workgroup) before releasing the
-// others, so per-step bookkeeping costs no extra barrier. Every wait is
-// bounded: past `tlimit` wall-clock ticks the waiter raises the abort flag and
-// all workgroups leave the kernel at their next barrier. Returns false on abort.
+// Barriers. The last workgroup to arrive runs `serial` (whole workgroup)
+// before releasing the others, so per-step bookkeeping costs no extra
+// barrier. Every wait is bounded: past `tlimit` wall-clock ticks the waiter
+// raises the abort flag and all workgroups leave the kernel at their next
+// barrier. Barrier calls return false on abort.
 
 template <class P>
-__device__ bool spin_until(const GPTR KArgs& a, P flag, ull target) {
+__device__ bool spin_until(const KArgs& a, P flag, ull target) {
   const long long t0 = wall_clock64();
   unsigned spins = 0;
   while (ld_agent(flag) < target) {
     __builtin_amdgcn_s_sleep(1);
     if ((++spins & 63) == 0) {
-      if (__hip_atomic_load(&a.ctl->abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+      if (__hip_atomic_load(&a.grid->abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
       if ((ull)(wall_clock64() - t0) > a.tlimit) {
-        __hip_atomic_store(&a.ctl->abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.grid->abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return false;
       }
     }
@@ -318,24 +362,23 @@ __device__ bool spin_until(const GPTR KArgs& a, P flag, ull target) {
   return true;
 }
 
-__device__ __forceinline__ bool finish_sync(const GPTR KArgs& a, Shared& sh) {
+__device__ __forceinline__ bool finish_sync(const KArgs& a, Shared& sh) {
   if (threadIdx.x == 0)
-    sh.abort = __hip_atomic_load(&a.ctl->abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    sh.abort = __hip_atomic_load(&a.grid->abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
   __syncthreads();
   const bool ok = sh.abort == 0;
   __syncthreads();
   return ok;
 }
 
-// Flat barrier (every workgroup releases and acquires at agent scope); used
-// once, before the XCD groups are known.
+// Flat barrier over the whole grid (every workgroup releases and acquires at
+// agent scope); used once, before the teams and XCD groups are known.
 template <class Serial>
-__device__ bool flat_sync(const GPTR KArgs& a, Shared& sh, Serial serial) {
-  GPTR Control* ctl = a.ctl;
+__device__ bool flat_sync(const KArgs& a, Shared& sh, Serial serial) {
+  GridCtl* gc = a.grid;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const ull prev =
-        __hip_atomic_fetch_add(&ctl->arrive_flat.v, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const ull prev = __hip_atomic_fetch_add(&gc->arrive_flat.v, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     sh.last = prev == (ull)a.G - 1ull;
     if (sh.last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
@@ -343,38 +386,43 @@ __device__ bool flat_sync(const GPTR KArgs& a, Shared& sh, Serial serial) {
   if (sh.last) {
     serial();
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(&ctl->gen_flat.v, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) __hip_atomic_store(&gc->gen_flat.v, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   } else if (threadIdx.x == 0) {
-    spin_until(a, &ctl->gen_flat.v, 1ull);
+    spin_until(a, &gc->gen_flat.v, 1ull);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   return finish_sync(a, sh);
 }
 
-// Hierarchical barrier (see the file comment).
+// Team barrier (see the file comment).
 template <class Serial>
-__device__ bool grid_sync(const GPTR KArgs& a, Shared& sh, Sync& sy, Serial serial) {
-  GPTR Control* ctl = a.ctl;
+__device__ bool team_sync(const KArgs& a, Shared& sh, Team& tm, Serial serial) {
   __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached L2
   __syncthreads();
-  ++sy.epoch;
+  ++tm.epoch;
   if (threadIdx.x == 0) {
     sh.last = 0;
-    const ull prev = atom_add(&ctl->grp_arrive[sy.xcc].v, 1ull);
-    if (prev == sy.epoch * sy.gsz - 1ull) {
-      // Last of this XCD: publish the XCD's L2 contents, then arrive globally.
+    if (tm.member_release) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const ull prev = atom_add(tm.l1_arrive, 1ull);
+    if (prev == tm.epoch * tm.l1_size - 1ull) {
+      // Last of the first-level group: publish its L2 contents.
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      const ull p2 = atom_add(&ctl->arrive.v, 1ull);
-      if (p2 == sy.epoch * sy.ngroups - 1ull) {
+      if (tm.l2_arrive) {
+        const ull p2 = atom_add(tm.l2_arrive, 1ull);
+        if (p2 == tm.epoch * tm.l2_size - 1ull) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          sh.last = 1;
+        } else {
+          spin_until(a, tm.l2_gen, tm.epoch);
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          st_agent(tm.l1_gen, tm.epoch);
+        }
+      } else {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         sh.last = 1;
-      } else {
-        spin_until(a, &ctl->gen.v, sy.epoch);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        st_agent(&ctl->grp_gen[sy.xcc].v, sy.epoch);
       }
     } else {
-      spin_until(a, &ctl->grp_gen[sy.xcc].v, sy.epoch);
+      spin_until(a, tm.l1_gen, tm.epoch);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
   }
@@ -385,8 +433,8 @@ __device__ bool grid_sync(const GPTR KArgs& a, Shared& sh, Sync& sy, Serial seri
     __syncthreads();
     if (threadIdx.x == 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      st_agent(&ctl->gen.v, sy.epoch);
-      st_agent(&ctl->grp_gen[sy.xcc].v, sy.epoch);
+      if (tm.l2_arrive) st_agent(tm.l2_gen, tm.epoch);
+      st_agent(tm.l1_gen, tm.epoch);
     }
   }
   return finish_sync(a, sh);
@@ -398,8 +446,8 @@ struct NoSerial {
 
 // k-th smallest (1-based) of vals[0..s) by MSD radix selection over the bits
 // below the highest bit where min and max differ. Whole workgroup.
-template <class P>
-__device__ __noinline__ ull wg_select_kth(P vals, ull s, ull k, Shared& sh) {
+__device__ __noinline__ ull wg_select_kth(const ull* vals, ull s, ull k) {
+  Shared& sh = g_sh;
   const unsigned tid = threadIdx.x;
   ull mn = INF, negmax = INF;  // max(x) = ~min(~x)
   for (ull i = tid; i < s; i += WG) {
@@ -465,36 +513,49 @@ __device__ __noinline__ ull wg_select_kth(P vals, ull s, ull k, Shared& sh) {
 }
 
 // ---------------------------------------------------------------------------
-// Extract helpers.
+// Phase helpers.
 
-// Record one extracted hub vertex: its arcs become chunk tasks shared by all
-// workgroups in Relax.
-__device__ __noinline__ void push_hub(const GPTR KArgs& a, GPTR StepSlot* S, int32_t v) {
+// Record one extracted hub vertex: its arcs become chunk tasks shared by the
+// team in Relax, each carrying the key the vertex was extracted with.
+__device__ __noinline__ void push_hub(const KArgs& a, ull* H, StepSlot* S, int32_t v, ull d) {
   const ull deg = (ull)(a.off[v + 1] - a.off[v]);
   const ull nch = (deg + a.chunk_edges - 1) / a.chunk_edges;
   const ull base = atom_add(&S->h_count, nch);
-  for (ull c = 0; c < nch; ++c) a.H[base + c] = ((ull)(uint32_t)v << 32) | c;
+  for (ull c = 0; c < nch; ++c) {
+    H[2 * (base + c)] = ((ull)(uint32_t)v << 32) | c;
+    H[2 * (base + c) + 1] = d;
+  }
 }
 
 // Relax one arc (S3 + S4). Returns true when v became a new queue member.
 // Filter: a plain read of delta[v] (possibly stale, but never smaller than
 // the current value) showing nd >= delta[v] means the WriteMin cannot succeed,
 // so the atomic is skipped.
-__device__ __forceinline__ bool relax_arc(const GPTR KArgs& a, ull& succ, ull& minnew, int32_t v, ull nd) {
-  if (a.filter && !(nd < ld_plain(&a.dist[v]))) return false;
-  const ull old = atom_min(&a.dist[v], nd);
+__device__ __forceinline__ bool relax_arc(const KArgs& a, ull* dist, ull* bitmap, ull& succ, ull& minnew, int32_t v,
+                                          ull nd) {
+  if (a.filter && !(nd < ld_plain(&dist[v]))) return false;
+  const ull old = atom_min(&dist[v], nd);
   if (!(nd < old)) return false;
   ++succ;
   minnew = umin(minnew, nd);
   const ull bit = 1ull << (v & 63);
-  return !(atom_or(&a.bitmap[v >> 6], bit) & bit);
+  return !(atom_or(&bitmap[v >> 6], bit) & bit);
 }
 
-// ---------------------------------------------------------------------------
-// Phases. Each is a separate (not inlined) function so that registers are
-// allocated per phase rather than for the union of all of them.
-
-__shared__ Shared g_sh;
+// Append the flagged entries of each lane to the next explicit list with one
+// atomic per workgroup; entries past the list capacity are dropped (the
+// reserved count then exceeds the capacity and the list is not used).
+template <int K>
+__device__ __forceinline__ void list_append(const KArgs& a, StepSlot* S, int32_t* Lnext, const int32_t (&v)[K],
+                                            unsigned mask) {
+  ull o = wg_reserve(g_sh, &S->list_next, (uint32_t)__popc(mask));
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if ((mask >> k) & 1u) {
+      if (o < a.lcap) Lnext[o] = v[k];
+      ++o;
+    }
+}
 
 // Sample size and probe count of a rho step (App. B: s = c (q / rho + log q),
 // c = 10, log q = 1 + log2(q + 1)); a bitmap step probes random vertex ids and
@@ -510,13 +571,15 @@ __device__ __noinline__ ull rho_probes(ull q, ull rho_eff, ull n, bool dense, ui
   return (ull)p;
 }
 
-// S1 for rho-stepping: draw the samples of the queue's keys (App. B). The
-// selection itself runs in the following barrier's serial section.
-__device__ __noinline__ void phase_sample(const GPTR KArgs* __restrict__ A, GPTR StepSlot* S, const GPTR int32_t* Lcur,
-                                          ull q, bool dense, ull probes, ull tseed) {
+// S1 for rho-stepping: draw this workgroup's share of the samples of the
+// queue's keys (App. B). The selection runs in the following barrier's serial
+// section.
+__device__ __noinline__ void phase_sample(const KArgs& a, const ull* dist, StepSlot* S,
+                                          const int32_t* Lcur, ull q, bool dense, ull probes, ull tseed) {
+  const Team& tm = g_tm;
   Shared& sh = g_sh;
-  const ull b = blockIdx.x, G = A->G, nthreads = G * WG, n = (ull)A->n;
-  for (ull base = b * WG; base < probes; base += nthreads) {
+  const ull n = (ull)a.n, stride = tm.T * WG;
+  for (ull base = tm.rank * WG; base < probes; base += stride) {
     const ull j = base + threadIdx.x;
     bool acc = false;
     ull d = 0;
@@ -524,18 +587,18 @@ __device__ __noinline__ void phase_sample(const GPTR KArgs* __restrict__ A, GPTR
       const ull r = splitmix(tseed, j);
       if (dense) {
         const ull v = below(r, n);
-        if ((ld_agent(&A->bitmap[v >> 6]) >> (v & 63)) & 1ull) {
+        if ((ld_agent(&tm.bitmap[v >> 6]) >> (v & 63)) & 1ull) {
           acc = true;
-          d = ld_agent(&A->dist[v]);
+          d = ld_agent(&dist[v]);
         }
       } else {
         const int32_t v = ld_agent_i32(&Lcur[below(r, q)]);
         acc = true;
-        d = ld_agent(&A->dist[v]);
+        d = ld_agent(&dist[v]);
       }
     }
     const ull pos = wg_reserve(sh, &S->nsamples, acc ? 1u : 0u);
-    if (acc) A->samples[pos] = d;
+    if (acc) tm.samples[pos] = d;
   }
 }
 
@@ -545,26 +608,85 @@ struct ExtractOut {
   ull minkept;    // min key of the members left in Q
 };
 
-// S2, bitmap step. Workgroup b owns the blocks of BLOCK_WORDS words
-// b, b + G, b + 2G, ... (interleaved, so that the high-degree vertices
+// Extraction decisions of one round: v[k] (or -1), keys d[k], hub flags.
+// Small candidates are extracted while the F segment has room; the rest stay
+// in Q (a team whose segments cannot hold every candidate of a step extracts
+// the first segcap of each segment and leaves the others for the next step).
+template <int K>
+__device__ __forceinline__ void extract_round(const KArgs& a, const Team& tm, StepSlot* S, int32_t* Lnext,
+                                              ull theta, bool emit, bool atomic_clear, const int32_t (&v)[K],
+                                              const ull (&d)[K], unsigned hubs, ExtractOut& o, ull& clear) {
+  Shared& sh = g_sh;
+  uint32_t ncand = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (v[k] >= 0 && d[k] <= theta && !((hubs >> k) & 1u)) ++ncand;
+  uint32_t total;
+  const uint32_t first = o.fcnt + wg_scan(sh, ncand, total);
+  const ull room = a.segcap - o.fcnt;
+  uint32_t slot = first;
+  unsigned keep = 0;
+  int32_t ev[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    ev[k] = -1;
+    if (v[k] < 0) continue;
+    const ull bit = 1ull << (v[k] & 63);
+    bool ext = d[k] <= theta;
+    if (ext && !((hubs >> k) & 1u)) {
+      if (slot < a.segcap) {
+        tm.Fb[slot] = v[k];
+        if (a.snapshot) tm.FDb[slot] = d[k];
+      } else {
+        ext = false;
+      }
+      ++slot;
+    }
+    if (ext) {
+      if (atomic_clear) {
+        atom_and(&tm.bitmap[v[k] >> 6], ~bit);
+      } else {
+        clear |= bit;
+      }
+      ++o.x;
+      if (a.xcount) ev[k] = v[k];
+      if ((hubs >> k) & 1u) push_hub(a, tm.H, S, v[k], d[k]);
+    } else {
+      o.minkept = umin(o.minkept, d[k]);
+      keep |= 1u << k;
+    }
+  }
+  o.fcnt += (uint32_t)umin((ull)total, room);
+  if (emit) list_append(a, S, Lnext, v, keep);
+  if (a.xcount) {
+    uint32_t* xc = a.xcount + ld_agent(&tm.ctl->query) * (ull)a.n;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (ev[k] >= 0) xc[a.perm ? a.perm[ev[k]] : ev[k]] += 1u;
+  }
+}
+
+// S2, bitmap step. Within the team, rank r owns the blocks of BLOCK_WORDS
+// words r, r + T, r + 2T, ... (interleaved, so that the high-degree vertices
 // numbered first are spread over all workgroups). Each lane owns one word;
 // its members are read in rounds of BATCH keys.
-__device__ __noinline__ ExtractOut phase_extract_dense(const GPTR KArgs* __restrict__ A, GPTR StepSlot* S, GPTR int32_t* Fb,
-                                                       GPTR int32_t* Lnext, ull theta, bool emit) {
-  Shared& sh = g_sh;
-  const ull b = blockIdx.x, G = A->G, nw = A->nwords;
+__device__ __noinline__ ExtractOut phase_extract_dense(const KArgs& a, const ull* dist, StepSlot* S,
+                                                       int32_t* Lnext, ull theta, bool emit) {
+  const Team& tm = g_tm;
+  const ull nw = a.nwords, T = tm.T;
   const ull nblocks = (nw + BLOCK_WORDS - 1) / BLOCK_WORDS;
   constexpr ull BLOCKS_PER_ROUND = WG / BLOCK_WORDS;
   ExtractOut o{0, 0, INF};
-  for (ull r0 = b; r0 < nblocks; r0 += G * BLOCKS_PER_ROUND) {
-    const ull blk = r0 + G * (threadIdx.x / BLOCK_WORDS);
+  for (ull r0 = tm.rank; r0 < nblocks; r0 += T * BLOCKS_PER_ROUND) {
+    const ull blk = r0 + T * (threadIdx.x / BLOCK_WORDS);
     const ull wi = blk * BLOCK_WORDS + (threadIdx.x % BLOCK_WORDS);
-    const ull word = (blk < nblocks && wi < nw) ? ld_agent(&A->bitmap[wi]) : 0ull;
-    const ull hubw = word ? ld_plain(&A->hubmask[wi]) : 0ull;
+    const ull word = (blk < nblocks && wi < nw) ? ld_agent(&tm.bitmap[wi]) : 0ull;
+    const ull hubw = word ? ld_plain(&a.hubmask[wi]) : 0ull;
     ull rest = word, clear = 0;
     while (__syncthreads_or(rest != 0)) {
       int32_t v[BATCH];
       ull d[BATCH];
+      unsigned hubs = 0;
 #pragma unroll
       for (int k = 0; k < BATCH; ++k) {
         v[k] = -1;
@@ -572,100 +694,44 @@ __device__ __noinline__ ExtractOut phase_extract_dense(const GPTR KArgs* __restr
           const int bit = __ffsll((long long)rest) - 1;
           rest &= rest - 1;
           v[k] = (int32_t)(wi * 64 + bit);
+          if ((hubw >> bit) & 1ull) hubs |= 1u << k;
         }
       }
 #pragma unroll
-      for (int k = 0; k < BATCH; ++k) d[k] = v[k] >= 0 ? ld_agent(&A->dist[v[k]]) : INF;
-      uint32_t nsmall = 0, nkeep = 0;
-#pragma unroll
-      for (int k = 0; k < BATCH; ++k) {
-        if (v[k] < 0) continue;
-        const ull bit = 1ull << (v[k] & 63);
-        if (d[k] <= theta) {
-          clear |= bit;
-          ++o.x;
-          if (A->xcount) A->xcount[A->perm ? A->perm[v[k]] : v[k]] += 1u;
-          if (hubw & bit) {
-            push_hub(*A, S, v[k]);
-          } else {
-            ++nsmall;
-          }
-        } else {
-          o.minkept = umin(o.minkept, d[k]);
-          ++nkeep;
-        }
-      }
-      uint32_t total;
-      uint32_t fo = o.fcnt + wg_scan(sh, nsmall, total);
-      o.fcnt += total;
-      ull ko = emit ? wg_reserve(sh, &S->list_next, nkeep) : 0;
-#pragma unroll
-      for (int k = 0; k < BATCH; ++k) {
-        if (v[k] < 0) continue;
-        if (d[k] <= theta) {
-          if (!((hubw >> (v[k] & 63)) & 1ull)) Fb[fo++] = v[k];
-        } else if (emit) {
-          Lnext[ko++] = v[k];
-        }
-      }
+      for (int k = 0; k < BATCH; ++k) d[k] = v[k] >= 0 ? ld_agent(&dist[v[k]]) : INF;
+      extract_round(a, tm, S, Lnext, theta, emit, false, v, d, hubs, o, clear);
     }
-    if (clear) A->bitmap[wi] = word & ~clear;  // this lane owns word wi
+    if (clear) tm.bitmap[wi] = word & ~clear;  // this lane owns word wi
   }
   return o;
 }
 
 // S2, list step: this workgroup's contiguous slice of the explicit list.
-__device__ __noinline__ ExtractOut phase_extract_list(const GPTR KArgs* __restrict__ A, GPTR StepSlot* S, GPTR int32_t* Fb,
-                                                      const GPTR int32_t* Lcur, GPTR int32_t* Lnext, ull q, ull theta,
+__device__ __noinline__ ExtractOut phase_extract_list(const KArgs& a, const ull* dist, StepSlot* S,
+                                                      const int32_t* Lcur, int32_t* Lnext, ull q, ull theta,
                                                       bool emit) {
-  Shared& sh = g_sh;
-  const ull b = blockIdx.x, G = A->G;
-  const ull lo = b * q / G, hi = (b + 1) * q / G;
+  const Team& tm = g_tm;
+  const ull lo = tm.rank * q / tm.T, hi = (tm.rank + 1) * q / tm.T;
   ExtractOut o{0, 0, INF};
+  ull unused = 0;
   for (ull e0 = lo; e0 < hi; e0 += (ull)WG * UNROLL) {
     int32_t v[UNROLL];
     ull d[UNROLL];
+    unsigned hubs = 0;
 #pragma unroll
     for (int k = 0; k < UNROLL; ++k) {
       const ull i = e0 + (ull)k * WG + threadIdx.x;
       v[k] = i < hi ? ld_agent_i32(&Lcur[i]) : -1;
     }
 #pragma unroll
-    for (int k = 0; k < UNROLL; ++k) d[k] = v[k] >= 0 ? ld_agent(&A->dist[v[k]]) : INF;
-    uint32_t nsmall = 0, nkeep = 0;
-    unsigned hubs = 0;
-#pragma unroll
     for (int k = 0; k < UNROLL; ++k) {
-      if (v[k] < 0) continue;
-      const ull bit = 1ull << (v[k] & 63);
-      if (d[k] <= theta) {
-        atom_and(&A->bitmap[v[k] >> 6], ~bit);
-        ++o.x;
-        if (A->xcount) A->xcount[A->perm ? A->perm[v[k]] : v[k]] += 1u;
-        if (ld_plain(&A->hubmask[v[k] >> 6]) & bit) {
-          hubs |= 1u << k;
-          push_hub(*A, S, v[k]);
-        } else {
-          ++nsmall;
-        }
-      } else {
-        o.minkept = umin(o.minkept, d[k]);
-        ++nkeep;
+      d[k] = INF;
+      if (v[k] >= 0) {
+        d[k] = ld_agent(&dist[v[k]]);
+        if ((ld_plain(&a.hubmask[v[k] >> 6]) >> (v[k] & 63)) & 1ull) hubs |= 1u << k;
       }
     }
-    uint32_t total;
-    uint32_t fo = o.fcnt + wg_scan(sh, nsmall, total);
-    o.fcnt += total;
-    ull ko = emit ? wg_reserve(sh, &S->list_next, nkeep) : 0;
-#pragma unroll
-    for (int k = 0; k < UNROLL; ++k) {
-      if (v[k] < 0) continue;
-      if (d[k] <= theta) {
-        if (!((hubs >> k) & 1u)) Fb[fo++] = v[k];
-      } else if (emit) {
-        Lnext[ko++] = v[k];
-      }
-    }
+    extract_round(a, tm, S, Lnext, theta, emit, true, v, d, hubs, o, unused);
   }
   return o;
 }
@@ -676,58 +742,52 @@ struct RelaxAcc {
 
 // Relax UNROLL arcs per lane (ev = packed arc or INF, dd = key of its tail)
 // and append new queue members to the next list when it is being built.
-__device__ __forceinline__ void relax_batch(const GPTR KArgs* __restrict__ A, GPTR StepSlot* S, GPTR int32_t* Lnext, bool emit,
-                                            RelaxAcc& acc, const ull (&ev)[UNROLL], const ull (&dd)[UNROLL]) {
-  uint32_t nf = 0;
+__device__ __forceinline__ void relax_batch(const KArgs& a, const Team& tm, ull* dist, StepSlot* S, int32_t* Lnext,
+                                            bool emit, RelaxAcc& acc, const ull (&ev)[UNROLL],
+                                            const ull (&dd)[UNROLL]) {
   int32_t fv[UNROLL];
+  unsigned mask = 0;
 #pragma unroll
   for (int k = 0; k < UNROLL; ++k) {
-    fv[k] = -1;
+    fv[k] = (int32_t)(uint32_t)ev[k];
     if (ev[k] == INF) continue;
     ++acc.edges;
-    const int32_t v = (int32_t)(uint32_t)ev[k];
-    if (relax_arc(*A, acc.succ, acc.minnew, v, dd[k] + (ev[k] >> 32))) {
+    if (relax_arc(a, dist, tm.bitmap, acc.succ, acc.minnew, fv[k], dd[k] + (ev[k] >> 32))) {
       ++acc.fresh;
-      fv[k] = v;
-      ++nf;
+      mask |= 1u << k;
     }
   }
-  if (emit) {
-    ull o = wg_reserve(g_sh, &S->list_next, nf);
-#pragma unroll
-    for (int k = 0; k < UNROLL; ++k)
-      if (fv[k] >= 0) Lnext[o++] = fv[k];
-  }
+  if (emit) list_append(a, S, Lnext, fv, mask);
 }
 
-// S3 + S4: the hub chunks (strided over workgroups), then this workgroup's
-// own extracted vertices. Writes the workgroup's partial counts.
-__device__ __noinline__ void phase_relax(const GPTR KArgs* __restrict__ A, GPTR StepSlot* S, const GPTR int32_t* Fb,
-                                         GPTR int32_t* Lnext, bool emit, ExtractOut ex) {
+// S3 + S4: the team's hub chunks (strided over its workgroups), then this
+// workgroup's own extracted vertices. Writes the workgroup's partial counts.
+__device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S, int32_t* Lnext,
+                                         bool emit, ExtractOut ex) {
+  const Team& tm = g_tm;
   Shared& sh = g_sh;
   const unsigned tid = threadIdx.x;
-  const ull b = blockIdx.x, G = A->G;
   const long long t_start = wall_clock64();
   RelaxAcc acc{0, 0, 0, INF};
   const ull nH = ld_agent(&S->h_count);
-  const ull CH = A->chunk_edges;
-  for (ull item = b; item < nH; item += G) {
-    const ull task = ld_agent(&A->H[item]);
+  const ull CH = a.chunk_edges;
+  for (ull item = tm.rank; item < nH; item += tm.T) {
+    const ull task = ld_agent(&tm.H[2 * item]);
     const int32_t u = (int32_t)(task >> 32);
+    const ull du = a.snapshot ? ld_agent(&tm.H[2 * item + 1]) : ld_agent(&dist[u]);
     const ull c = task & 0xffffffffull;
-    const ull rb = (ull)A->off[u], re = (ull)A->off[u + 1];
+    const ull rb = (ull)a.off[u], re = (ull)a.off[u + 1];
     const ull beg = rb + c * CH;
     const ull end = umin(beg + CH, re);
-    const ull du = ld_agent(&A->dist[u]);
     for (ull e0 = beg; e0 < end; e0 += (ull)WG * UNROLL) {
       ull ev[UNROLL], dd[UNROLL];
 #pragma unroll
       for (int k = 0; k < UNROLL; ++k) {
         const ull e = e0 + (ull)k * WG + tid;
-        ev[k] = e < end ? A->edges[e] : INF;
+        ev[k] = e < end ? a.edges[e] : INF;
         dd[k] = du;
       }
-      relax_batch(A, S, Lnext, emit, acc, ev, dd);
+      relax_batch(a, tm, dist, S, Lnext, emit, acc, ev, dd);
     }
   }
   for (uint32_t j0 = 0; j0 < ex.fcnt; j0 += WG) {
@@ -735,10 +795,10 @@ __device__ __noinline__ void phase_relax(const GPTR KArgs* __restrict__ A, GPTR 
     uint32_t deg = 0;
     ull rb = 0, du = 0;
     if (j < ex.fcnt) {
-      const int32_t u = Fb[j];
-      rb = (ull)A->off[u];
-      deg = (uint32_t)((ull)A->off[u + 1] - rb);
-      du = ld_agent(&A->dist[u]);
+      const int32_t u = tm.Fb[j];
+      rb = (ull)a.off[u];
+      deg = (uint32_t)((ull)a.off[u + 1] - rb);
+      du = a.snapshot ? tm.FDb[j] : ld_agent(&dist[u]);
     }
     uint32_t total;
     const uint32_t excl = wg_scan(sh, deg, total);
@@ -758,11 +818,11 @@ __device__ __noinline__ void phase_relax(const GPTR KArgs* __restrict__ A, GPTR 
 #pragma unroll
           for (int step = WG / 2; step > 0; step >>= 1)
             if (sh.pre[lo + step] <= e) lo += step;
-          ev[k] = A->edges[sh.beg[lo] + (e - sh.pre[lo])];
+          ev[k] = a.edges[sh.beg[lo] + (e - sh.pre[lo])];
           dd[k] = sh.du[lo];
         }
       }
-      relax_batch(A, S, Lnext, emit, acc, ev, dd);
+      relax_batch(a, tm, dist, S, Lnext, emit, acc, ev, dd);
     }
     __syncthreads();
   }
@@ -782,21 +842,22 @@ __device__ __noinline__ void phase_relax(const GPTR KArgs* __restrict__ A, GPTR 
     p.minnew = acc.minnew;
     p.busy = (ull)(wall_clock64() - t_start);
     p.pad = 0;
-    A->parts[b] = p;
+    a.parts[blockIdx.x] = p;
   }
 }
 
-// Serial section of the step's last barrier: sum the partials, publish the
-// step totals, clear the slot two steps ahead, update stats and the trace.
-__device__ __noinline__ void step_bookkeeping(const GPTR KArgs* __restrict__ A, GPTR StepSlot* S, ull t, ull q, ull theta,
+// Serial section of the step's last barrier: sum the partials of the team's
+// workgroups, publish the step totals, clear the slot two steps ahead, update
+// stats and the trace.
+__device__ __noinline__ void step_bookkeeping(const KArgs& a, StepSlot* S, ull t, ull q, ull theta,
                                               unsigned flags) {
+  const Team& tm = g_tm;
   Shared& sh = g_sh;
   const unsigned tid = threadIdx.x;
-  GPTR Control* ctl = A->ctl;
-  const ull G = A->G;
+  TeamCtl* tc = tm.ctl;
   ull x = 0, e = 0, s = 0, f = 0, mn = INF, busy = 0, negbusy = INF;
-  for (ull i = tid; i < G; i += WG) {
-    const ull* p = reinterpret_cast<const ull*>(&A->parts[i]);
+  for (ull r = tid; r < tm.T; r += WG) {
+    const ull* p = reinterpret_cast<const ull*>(&a.parts[tm.id + r * a.nteams]);
     x += ld_agent(p + 0);
     mn = umin(mn, ld_agent(p + 1));
     e += ld_agent(p + 2);
@@ -813,7 +874,7 @@ __device__ __noinline__ void step_bookkeeping(const GPTR KArgs* __restrict__ A, 
     wg_reduce4(sh, f, busy, z0, negbusy);
   }
   if (tid < 16) {
-    ull* z = reinterpret_cast<ull*>(&ctl->slot[(t + 2) % 3]);
+    ull* z = reinterpret_cast<ull*>(&tc->slot[(t + 2) % 3]);
     z[tid] = 0ull;
   }
   if (tid == 0) {
@@ -822,15 +883,15 @@ __device__ __noinline__ void step_bookkeeping(const GPTR KArgs* __restrict__ A, 
     S->min_next = mn;
     S->edges = e;
     S->successes = s;
-    ctl->st_steps += 1;
-    ctl->st_extracted += x;
-    ctl->st_edges += e;
-    ctl->st_success += s;
-    ctl->st_dense += (flags & 1u) ? 1 : 0;
-    ctl->st_sampled += (flags & 4u) ? 1 : 0;
-    ctl->relax_busy_max += ~negbusy;
-    ctl->relax_busy_sum += busy;
-    if (A->trace && t < A->trace_cap) {
+    tc->st_steps += 1;
+    tc->st_extracted += x;
+    tc->st_edges += e;
+    tc->st_success += s;
+    tc->st_dense += (flags & 1u) ? 1 : 0;
+    tc->st_sampled += (flags & 4u) ? 1 : 0;
+    tc->relax_busy_max += ~negbusy;
+    tc->relax_busy_sum += busy;
+    if (a.trace && tc->query == 0 && t < a.trace_cap) {
       sssp_step_record r;
       r.theta = theta;
       r.q = q;
@@ -839,7 +900,7 @@ __device__ __noinline__ void step_bookkeeping(const GPTR KArgs* __restrict__ A, 
       r.successes = s;
       r.flags = flags;
       r.samples = (flags & 4u) ? (uint32_t)ld_agent(&S->nsamples) : 0u;
-      A->trace[t] = r;
+      a.trace[t] = r;
     }
   }
 }
@@ -847,21 +908,31 @@ __device__ __noinline__ void step_bookkeeping(const GPTR KArgs* __restrict__ A, 
 // ---------------------------------------------------------------------------
 // The persistent kernel.
 
-__global__ __launch_bounds__(WG, 4) void stepping_kernel(const GPTR KArgs* __restrict__ A) {
+__global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict__ A) {
   Shared& sh = g_sh;
-  const GPTR KArgs& a = *A;
+  const KArgs& a = *A;
   const unsigned tid = threadIdx.x;
   const ull b = blockIdx.x;
-  const ull G = a.G;
-  const ull nthreads = G * WG;
-  const ull gtid = b * WG + tid;
   const ull n = (ull)a.n;
-  GPTR Control* ctl = a.ctl;
-  Sync sy;
-  sy.xcc = __builtin_amdgcn_s_getreg(20 | (15 << 11)) & (MAX_XCC - 1);  // hwreg XCC_ID
-  GPTR int32_t* Fb = a.F + b * a.segcap;
+  GridCtl* gc = a.grid;
+  const unsigned xcc = __builtin_amdgcn_s_getreg(20 | (15 << 11)) & (MAX_XCC - 1);  // hwreg XCC_ID
 
-  // Phase clock: workgroup 0 reads the wall clock as it leaves each barrier.
+  Team tm;
+  tm.id = b % a.nteams;
+  tm.rank = b / a.nteams;
+  tm.T = a.G / a.nteams;
+  tm.ctl = a.teams + tm.id;
+  tm.bitmap = a.bitmap + tm.id * a.nwords;
+  tm.H = a.H + tm.id * 2 * a.hcap;
+  tm.L = a.L + tm.id * 2 * a.lcap;
+  tm.samples = a.samples + tm.id * a.probe_cap;
+  tm.Fb = a.F + b * a.segcap;
+  tm.FDb = a.FD + b * a.segcap;
+  tm.epoch = 0;
+  ull* dist = a.dist_int ? a.dist_int + tm.id * n : nullptr;
+
+  // Phase clock: the team's first workgroup reads the wall clock as it
+  // leaves each barrier.
   ull ph0 = 0, ph1 = 0, ph2 = 0, ph3 = 0;
   long long tmark = wall_clock64();
   auto lap = [&]() {
@@ -871,107 +942,152 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const GPTR KArgs* __res
     return d;
   };
 
-  // S0: delta = inf, Q empty; then delta[s] = 0 and Update(s).
-  if (tid == 0) atom_add(&ctl->grp_size[sy.xcc].v, 1ull);
-  for (ull i = gtid; i < n; i += nthreads) a.dist[i] = INF;
-  for (ull i = gtid; i < a.nwords; i += nthreads) a.bitmap[i] = 0;
+  // Register the XCD, check the round-robin placement, meet once.
+  if (tid == 0) {
+    atom_add(&gc->grp_size[xcc].v, 1ull);
+    if (xcc != (unsigned)(b % 8)) atom_add(&gc->mismatch.v, 1ull);
+  }
   {
-    auto seed_source = [&]() {
+    auto count_groups = [&]() {
       if (tid == 0) {
-        const int32_t s = a.inv ? a.inv[a.source] : a.source;
-        a.dist[s] = 0;
-        a.bitmap[s >> 6] = 1ull << (s & 63);
-        a.L0[0] = s;
         ull g = 0;
-        for (int x = 0; x < MAX_XCC; ++x) g += ctl->grp_size[x].v ? 1 : 0;
-        ctl->ngroups = g;
+        for (int x = 0; x < MAX_XCC; ++x) g += gc->grp_size[x].v ? 1 : 0;
+        gc->ngroups = g;
       }
     };
-    if (!flat_sync(a, sh, seed_source)) return;
-    sy.gsz = ld_agent(&ctl->grp_size[sy.xcc].v);
-    sy.ngroups = ld_agent(&ctl->ngroups);
-    ph0 += lap();
+    if (!flat_sync(a, sh, count_groups)) return;
   }
+  if (a.nteams == 1) {
+    tm.l1_arrive = &gc->grp_arrive[xcc].v;
+    tm.l1_gen = &gc->grp_gen[xcc].v;
+    tm.l1_size = ld_agent(&gc->grp_size[xcc].v);
+    tm.l2_arrive = &gc->arrive.v;
+    tm.l2_gen = &gc->gen.v;
+    tm.l2_size = ld_agent(&gc->ngroups);
+    tm.member_release = false;
+  } else {
+    tm.l1_arrive = &tm.ctl->arrive.v;
+    tm.l1_gen = &tm.ctl->gen.v;
+    tm.l1_size = tm.T;
+    tm.l2_arrive = nullptr;
+    tm.l2_gen = nullptr;
+    tm.l2_size = 0;
+    // Teams inside one XCD share an L2 unless the placement is unexpected.
+    tm.member_release = (a.nteams % 8 != 0) || ld_agent(&gc->mismatch.v) != 0;
+  }
+  if (tid == 0) g_tm = tm;
+  __syncthreads();
+  ph0 += lap();
 
-  ull q = 1, minq = 0, idelta = 0, dense_steps = 0;
-  bool list_valid = true;
+  for (;;) {
+    // Take the next source.
+    auto claim = [&]() {
+      if (tid == 0) tm.ctl->query = atom_add(&gc->next_query.v, 1ull);
+    };
+    if (!team_sync(a, sh, tm, claim)) return;
+    const ull qi = ld_agent(&tm.ctl->query);
+    if (qi >= (ull)a.n_src) break;
+    ull* out = a.dist_out + qi * n;
+    if (!a.dist_int) dist = out;
 
-  for (ull t = 0;; ++t) {
-    if (q == 0) break;
-    if (a.max_steps && t >= a.max_steps) {
-      if (b == 0 && tid == 0) ctl->status = ST_STEP_LIMIT;
-      break;
+    // S0: delta = inf, Q empty; then delta[s] = 0 and Update(s).
+    for (ull i = tm.rank * WG + tid; i < n; i += tm.T * WG) dist[i] = INF;
+    for (ull i = tm.rank * WG + tid; i < a.nwords; i += tm.T * WG) tm.bitmap[i] = 0;
+    {
+      auto seed_source = [&]() {
+        if (tid < 48) reinterpret_cast<ull*>(&tm.ctl->slot[0])[tid] = 0ull;
+        if (tid == 0) {
+          const int32_t src = a.srcs[qi];
+          const int32_t s = a.inv ? a.inv[src] : src;
+          dist[s] = 0;
+          tm.bitmap[s >> 6] = 1ull << (s & 63);
+          tm.L[0] = s;
+        }
+      };
+      if (!team_sync(a, sh, tm, seed_source)) return;
+      ph0 += lap();
     }
-    GPTR StepSlot* S = &ctl->slot[t % 3];
-    GPTR int32_t* Lcur = (t & 1) ? a.L1 : a.L0;
-    GPTR int32_t* Lnext = (t & 1) ? a.L0 : a.L1;
-    const bool dense = !list_valid;
-    const bool emit = q <= a.list_threshold;
 
-    // ---- S1: ExtDist ----
-    ull theta = INF;
-    bool sampled = false;
-    if (a.rule == SSSP_RULE_BF) {
-      theta = INF;
-    } else if (a.rule == SSSP_RULE_MIN) {
-      theta = minq;
-    } else if (a.rule == SSSP_RULE_DELTA_STAR) {
-      ull i = idelta + 1;
-      const ull skip = minq / a.delta + (minq % a.delta != 0);  // ceil(min / Delta)
-      if (skip > i) i = skip;
-      idelta = i;
-      ull prod;
-      theta = __builtin_mul_overflow(i, (ull)a.delta, &prod) ? INF : prod;
-    } else {
-      const ull rho_eff = (dense && dense_steps < 2) ? ((a.rho / 10) > 0 ? a.rho / 10 : 1) : a.rho;
-      if (q > rho_eff) {
-        sampled = true;
-        const ull probes = rho_probes(q, rho_eff, n, dense, a.sample_cap, a.probe_cap);
-        phase_sample(A, S, Lcur, q, dense, probes, splitmix(a.seed, t));
-        auto choose = [&]() {
-          const ull s = ld_agent(&S->nsamples);
-          ull th = INF;
-          if (s > 0) {
-            ull k = (rho_eff * s + q - 1) / q;  // ceil(rho * s / q)
-            if (k < 1) k = 1;
-            if (k > s) k = s;
-            th = wg_select_kth(a.samples, s, k, sh);
-          }
-          if (tid == 0) ctl->theta = th;
-        };
-        if (!grid_sync(a, sh, sy, choose)) return;
-        ph1 += lap();
-        theta = ld_agent(&ctl->theta);
+    ull q = 1, minq = 0, idelta = 0, dense_steps = 0;
+    bool list_valid = true;
+
+    for (ull t = 0;; ++t) {
+      if (q == 0) break;
+      if (a.max_steps && t >= a.max_steps) {
+        if (tm.rank == 0 && tid == 0) tm.ctl->status |= ST_STEP_LIMIT;
+        break;
       }
+      StepSlot* S = &tm.ctl->slot[t % 3];
+      int32_t* Lcur = tm.L + ((t & 1) ? a.lcap : 0);
+      int32_t* Lnext = tm.L + ((t & 1) ? 0 : a.lcap);
+      const bool dense = !list_valid;
+      const bool emit = q <= a.list_threshold;
+
+      // ---- S1: ExtDist ----
+      ull theta = INF;
+      bool sampled = false;
+      if (a.rule == SSSP_RULE_BF) {
+        theta = INF;
+      } else if (a.rule == SSSP_RULE_MIN) {
+        theta = minq;
+      } else if (a.rule == SSSP_RULE_DELTA_STAR) {
+        ull i = idelta + 1;
+        const ull skip = minq / a.delta + (minq % a.delta != 0);  // ceil(min / Delta)
+        if (skip > i) i = skip;
+        idelta = i;
+        ull prod;
+        theta = __builtin_mul_overflow(i, (ull)a.delta, &prod) ? INF : prod;
+      } else {
+        const ull rho_eff = (dense && dense_steps < 2) ? ((a.rho / 10) > 0 ? a.rho / 10 : 1) : a.rho;
+        if (q > rho_eff) {
+          sampled = true;
+          const ull probes = rho_probes(q, rho_eff, n, dense, a.sample_cap, a.probe_cap);
+          phase_sample(a, dist, S, Lcur, q, dense, probes, splitmix(a.seed ^ qi, t));
+          auto choose = [&]() {
+            const ull s = ld_agent(&S->nsamples);
+            ull th = INF;
+            if (s > 0) {
+              ull k = (rho_eff * s + q - 1) / q;  // ceil(rho * s / q)
+              if (k < 1) k = 1;
+              if (k > s) k = s;
+              th = wg_select_kth(tm.samples, s, k);
+            }
+            if (tid == 0) tm.ctl->theta = th;
+          };
+          if (!team_sync(a, sh, tm, choose)) return;
+          ph1 += lap();
+          theta = ld_agent(&tm.ctl->theta);
+        }
+      }
+
+      // ---- S2: Extract(theta) over this workgroup's slice ----
+      const ExtractOut ex = dense ? phase_extract_dense(a, dist, S, Lnext, theta, emit)
+                                  : phase_extract_list(a, dist, S, Lcur, Lnext, q, theta, emit);
+      if (!team_sync(a, sh, tm, NoSerial{})) return;
+      ph2 += lap();
+
+      // ---- S3/S4: Relax + Update ----
+      phase_relax(a, dist, S, Lnext, emit, ex);
+      const unsigned flags = (dense ? 1u : 0u) | (emit ? 2u : 0u) | (sampled ? 4u : 0u);
+      auto bookkeeping = [&]() { step_bookkeeping(a, S, t, q, theta, flags); };
+      if (!team_sync(a, sh, tm, bookkeeping)) return;
+      ph3 += lap();
+
+      // ---- S5: next queue state, identical in every workgroup of the team ----
+      q = q - ld_agent(&S->x_total) + ld_agent(&S->fresh_total);
+      minq = ld_agent(&S->min_next);
+      list_valid = emit && ld_agent(&S->list_next) <= a.lcap;
+      if (dense) ++dense_steps;
     }
-
-    // ---- S2: Extract(theta) over this workgroup's slice ----
-    const ExtractOut ex = dense ? phase_extract_dense(A, S, Fb, Lnext, theta, emit)
-                                : phase_extract_list(A, S, Fb, Lcur, Lnext, q, theta, emit);
-    if (!grid_sync(a, sh, sy, NoSerial{})) return;
-    ph2 += lap();
-
-    // ---- S3/S4: Relax + Update ----
-    phase_relax(A, S, Fb, Lnext, emit, ex);
-    const unsigned flags = (dense ? 1u : 0u) | (emit ? 2u : 0u) | (sampled ? 4u : 0u);
-    auto bookkeeping = [&]() { step_bookkeeping(A, S, t, q, theta, flags); };
-    if (!grid_sync(a, sh, sy, bookkeeping)) return;
-    ph3 += lap();
-
-    // ---- S5: next queue state, identical in every workgroup ----
-    q = q - ld_agent(&S->x_total) + ld_agent(&S->fresh_total);
-    minq = ld_agent(&S->min_next);
-    list_valid = emit;
-    if (dense) ++dense_steps;
+    // Distances back in the caller's vertex ids.
+    if (a.dist_int)
+      for (ull v = tm.rank * WG + tid; v < n; v += tm.T * WG) out[v] = ld_agent(&dist[a.inv[v]]);
   }
-  // Distances back in the caller's vertex ids.
-  if (a.inv)
-    for (ull v = gtid; v < n; v += nthreads) a.dist_out[v] = ld_agent(&a.dist[a.inv[v]]);
-  if (b == 0 && tid == 0) {
-    ctl->phase_ticks[0] = ph0;
-    ctl->phase_ticks[1] = ph1;
-    ctl->phase_ticks[2] = ph2;
-    ctl->phase_ticks[3] = ph3;
+  if (tm.rank == 0 && tid == 0) {
+    tm.ctl->phase_ticks[0] += ph0;
+    tm.ctl->phase_ticks[1] += ph1;
+    tm.ctl->phase_ticks[2] += ph2;
+    tm.ctl->phase_ticks[3] += ph3;
   }
 }
 
@@ -987,25 +1103,23 @@ __global__ void hubmask_kernel(const int64_t* off, ull n, ull nwords, uint32_t h
   }
 }
 
-__global__ void reset_control_kernel(Control* ctl) {
-  ull* p = reinterpret_cast<ull*>(ctl);
-  for (size_t i = threadIdx.x; i < sizeof(Control) / 8; i += blockDim.x) p[i] = 0;
+// Zero the control blocks before a solve (a kernel rather than a memset, so
+// the sequence stays valid under stream capture).
+__global__ void reset_control_kernel(ull* p, ull words) {
+  for (ull i = (ull)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (ull)gridDim.x * blockDim.x) p[i] = 0;
 }
-
-}  // namespace
-
-namespace {
 
 sssp_tuning default_tuning() {
   sssp_tuning t;
   std::memset(&t, 0, sizeof(t));
-  t.blocks_per_cu = 8;
+  t.blocks_per_cu = 4;
   t.hub_degree = 1024;
   t.chunk_edges = 4096;
   t.list_divisor = 64;
   t.sample_cap = 4096;
   t.probe_cap = 1u << 16;
   t.no_filter = 0;
+  t.teams = 0;
   return t;
 }
 
@@ -1022,44 +1136,78 @@ sssp_tuning resolve_tuning(const sssp_tuning* in) {
   return t;
 }
 
-// F segment size: a workgroup extracts at most the vertices of the blocks it
-// owns (bitmap steps) or of its list slice (list steps, at most ceil(n / G)).
-uint64_t segment_capacity(uint64_t nwords, uint32_t G) {
-  const uint64_t nblocks = (nwords + BLOCK_WORDS - 1) / BLOCK_WORDS;
-  return 64ull * BLOCK_WORDS * ((nblocks + G - 1) / G);
+// Workspace geometry of one solve.
+struct Geometry {
+  uint32_t G, nteams, T;
+  uint64_t nwords, segcap, hcap, lcap;
+};
+
+constexpr uint64_t TEAM_SEGMENT_CAP = 1ull << 20;  // F entries per workgroup when teams share the grid
+constexpr uint64_t TEAM_LIST_CAP = 1ull << 22;     // explicit-list entries per team when teams share the grid
+
+Geometry make_geometry(const sssp_graph* g, const sssp_tuning& tu, uint32_t G, uint32_t nteams) {
+  Geometry geo;
+  geo.G = G;
+  geo.nteams = nteams;
+  geo.T = G / nteams;
+  const uint64_t n = (uint64_t)g->n, m = (uint64_t)g->m;
+  geo.nwords = (n + 63) / 64;
+  // A workgroup extracts at most the vertices of the blocks it owns (bitmap
+  // steps) or of its list slice (list steps, at most ceil(n / T)).
+  const uint64_t nblocks = (geo.nwords + BLOCK_WORDS - 1) / BLOCK_WORDS;
+  geo.segcap = 64ull * BLOCK_WORDS * ((nblocks + geo.T - 1) / geo.T);
+  // Each vertex is extracted at most once per step and an extracted hub
+  // contributes ceil(deg / chunk) tasks: m / chunk + m / (hub_degree + 1) + 1
+  // bounds the tasks of one step.
+  geo.hcap = m / tu.chunk_edges + m / ((uint64_t)tu.hub_degree + 1) + 2;
+  geo.lcap = n;
+  if (nteams > 1) {
+    geo.segcap = std::min<uint64_t>(geo.segcap, TEAM_SEGMENT_CAP);
+    geo.lcap = std::min<uint64_t>(n, TEAM_LIST_CAP);
+  }
+  return geo;
 }
 
-sssp_status ensure_workspace(sssp_graph* g, const sssp_tuning& tu, uint32_t G, hipStream_t st) {
+uint64_t control_words(uint32_t nteams) { return (sizeof(GridCtl) + (uint64_t)nteams * sizeof(TeamCtl)) / 8; }
+
+sssp_status ensure_workspace(sssp_graph* g, const sssp_tuning& tu, const Geometry& geo, hipStream_t st) {
   if (g->ws_ready && g->ws_hub_degree == tu.hub_degree && g->ws_chunk == tu.chunk_edges &&
-      g->ws_probe_cap >= tu.probe_cap && g->ws_G == G)
+      g->ws_probe_cap >= tu.probe_cap && g->ws_G == geo.G && g->ws_teams == geo.nteams)
     return SSSP_OK;
   g->release_ws();
-  const uint64_t n = (uint64_t)g->n, m = (uint64_t)g->m;
-  const uint64_t nwords = (n + 63) / 64;
-  // H capacity: each vertex is extracted at most once per step, and an
-  // extracted hub contributes ceil(deg / chunk) tasks, so
-  // m / chunk + m / (hub_degree + 1) + 1 bounds the tasks of one step.
-  const uint64_t hcap = m / tu.chunk_edges + m / ((uint64_t)tu.hub_degree + 1) + 2;
-  if (g->relabelled) SSSP_HIP_TRY(g->dist_int.alloc(n * 8));
-  SSSP_HIP_TRY(g->bitmap.alloc(nwords * 8));
-  SSSP_HIP_TRY(g->hubmask.alloc(nwords * 8));
-  SSSP_HIP_TRY(g->F.alloc((uint64_t)G * segment_capacity(nwords, G) * 4));
-  SSSP_HIP_TRY(g->H.alloc(hcap * 8));
-  SSSP_HIP_TRY(g->L0.alloc(n * 4));
-  SSSP_HIP_TRY(g->L1.alloc(n * 4));
-  SSSP_HIP_TRY(g->samples.alloc((uint64_t)tu.probe_cap * 8));
-  SSSP_HIP_TRY(g->parts.alloc((uint64_t)G * sizeof(Part)));
-  SSSP_HIP_TRY(g->ctl.alloc(sizeof(Control)));
+  const uint64_t n = (uint64_t)g->n, nt = geo.nteams;
+  if (g->relabelled) SSSP_HIP_TRY(g->dist_int.alloc(nt * n * 8));
+  SSSP_HIP_TRY(g->bitmap.alloc(nt * geo.nwords * 8));
+  SSSP_HIP_TRY(g->hubmask.alloc(geo.nwords * 8));
+  SSSP_HIP_TRY(g->F.alloc((uint64_t)geo.G * geo.segcap * 4));
+  SSSP_HIP_TRY(g->FD.alloc((uint64_t)geo.G * geo.segcap * 8));
+  SSSP_HIP_TRY(g->H.alloc(nt * geo.hcap * 16));
+  SSSP_HIP_TRY(g->L.alloc(nt * 2 * geo.lcap * 4));
+  SSSP_HIP_TRY(g->samples.alloc(nt * (uint64_t)tu.probe_cap * 8));
+  SSSP_HIP_TRY(g->parts.alloc((uint64_t)geo.G * sizeof(Part)));
+  SSSP_HIP_TRY(g->ctl.alloc(control_words(geo.nteams) * 8));
   SSSP_HIP_TRY(g->args.alloc(sizeof(KArgs)));
   SSSP_HIP_TRY(hipHostMalloc(&g->hargs, sizeof(KArgs), hipHostMallocDefault));
-  hubmask_kernel<<<1024, 256, 0, st>>>((const int64_t*)g->off.p, n, nwords, tu.hub_degree, (ull*)g->hubmask.p);
+  hubmask_kernel<<<1024, 256, 0, st>>>((const int64_t*)g->off.p, n, geo.nwords, tu.hub_degree, (ull*)g->hubmask.p);
   SSSP_HIP_TRY(hipGetLastError());
   g->ws_ready = true;
   g->ws_hub_degree = tu.hub_degree;
   g->ws_chunk = tu.chunk_edges;
   g->ws_probe_cap = tu.probe_cap;
-  g->ws_G = G;
+  g->ws_G = geo.G;
+  g->ws_teams = geo.nteams;
   return SSSP_OK;
+}
+
+// Teams for n_src sources when the caller leaves it to the library: one
+// whole-grid team for a single source, otherwise the smallest power of two
+// >= 8 (so that each team sits on one XCD) that covers the sources, as long
+// as it divides the grid.
+uint32_t auto_teams(int32_t n_src, uint32_t G) {
+  if (n_src <= 1 || G % 8 != 0) return 1;
+  uint32_t t = 8;
+  while (t < (uint32_t)n_src && G % (2 * t) == 0) t <<= 1;
+  return t;
 }
 
 }  // namespace
@@ -1088,6 +1236,7 @@ sssp_status sssp_solve(const sssp_graph* gc, const int32_t* sources, int32_t n_s
     sssp_default_params(&p);
   }
   if (p.rule > SSSP_RULE_MIN) return fail(SSSP_ERR_INVALID_ARGUMENT, "unknown rule");
+  if (p.flags & ~SSSP_SOLVE_SNAPSHOT_KEYS) return fail(SSSP_ERR_INVALID_ARGUMENT, "unknown flags");
   if (p.rule == SSSP_RULE_RHO && p.rho == 0) return fail(SSSP_ERR_INVALID_ARGUMENT, "rho must be >= 1");
   if (p.rule == SSSP_RULE_DELTA_STAR && p.delta == 0) return fail(SSSP_ERR_INVALID_ARGUMENT, "delta must be >= 1");
   if (p.trace && p.trace_capacity == 0) return fail(SSSP_ERR_INVALID_ARGUMENT, "trace needs trace_capacity > 0");
@@ -1109,103 +1258,115 @@ sssp_status sssp_solve(const sssp_graph* gc, const int32_t* sources, int32_t n_s
   if (occ < 1) return fail(SSSP_ERR_NO_DEVICE, "stepping kernel cannot be resident");
   const uint32_t bpc = std::min<uint32_t>(tu.blocks_per_cu, (uint32_t)occ);
   const uint32_t G = bpc * (uint32_t)g->cus;
-  sssp_status ws = ensure_workspace(g, tu, G, st);
+  const uint32_t nteams = tu.teams ? tu.teams : auto_teams(n_src, G);
+  if (nteams > G || G % nteams != 0)
+    return fail(SSSP_ERR_INVALID_ARGUMENT, "teams must divide the grid of " + std::to_string(G) + " workgroups");
+  const Geometry geo = make_geometry(g, tu, G, nteams);
+  sssp_status ws = ensure_workspace(g, tu, geo, st);
   if (ws != SSSP_OK) return ws;
+  if ((uint64_t)n_src > g->ws_src_cap) {
+    SSSP_HIP_TRY(g->srcs.alloc((uint64_t)n_src * 4));
+    g->ws_src_cap = (uint64_t)n_src;
+  }
 
   KArgs a;
   std::memset(&a, 0, sizeof(a));
   a.n = g->n;
-  a.nwords = ((uint64_t)g->n + 63) / 64;
-  a.off = (decltype(a.off))g->off.p;
-  a.edges = (decltype(a.edges))g->edges.p;
-  a.perm = (decltype(a.perm))(g->relabelled ? g->perm.p : nullptr);
-  a.inv = (decltype(a.inv))(g->relabelled ? g->inv.p : nullptr);
-  a.hubmask = (decltype(a.hubmask))g->hubmask.p;
-  a.parts = (decltype(a.parts))g->parts.p;
-  a.segcap = segment_capacity(a.nwords, G);
-  a.bitmap = (decltype(a.bitmap))g->bitmap.p;
-  a.F = (decltype(a.F))g->F.p;
-  a.H = (decltype(a.H))g->H.p;
-  a.L0 = (decltype(a.L0))g->L0.p;
-  a.L1 = (decltype(a.L1))g->L1.p;
-  a.samples = (decltype(a.samples))g->samples.p;
-  a.ctl = (decltype(a.ctl))g->ctl.p;
+  a.nwords = geo.nwords;
+  a.off = (const int64_t*)g->off.p;
+  a.edges = (const ull*)g->edges.p;
+  a.hubmask = (const ull*)g->hubmask.p;
+  a.perm = g->relabelled ? (const int32_t*)g->perm.p : nullptr;
+  a.inv = g->relabelled ? (const int32_t*)g->inv.p : nullptr;
+  a.srcs = (const int32_t*)g->srcs.p;
+  a.dist_out = (ull*)dist;
+  a.dist_int = g->relabelled ? (ull*)g->dist_int.p : nullptr;
+  a.bitmap = (ull*)g->bitmap.p;
+  a.F = (int32_t*)g->F.p;
+  a.FD = (ull*)g->FD.p;
+  a.H = (ull*)g->H.p;
+  a.L = (int32_t*)g->L.p;
+  a.samples = (ull*)g->samples.p;
+  a.parts = (Part*)g->parts.p;
+  a.grid = (GridCtl*)g->ctl.p;
+  a.teams = (TeamCtl*)((char*)g->ctl.p + sizeof(GridCtl));
+  a.xcount = p.extract_counts;
+  a.trace = p.trace;
+  a.trace_cap = p.trace ? p.trace_capacity : 0;
   a.rho = p.rho;
   a.delta = p.delta ? p.delta : 1;
   a.seed = p.seed;
   a.max_steps = p.max_steps;
-  a.list_threshold = tu.list_divisor == 0xFFFFFFFFu ? 0 : (uint64_t)g->n / tu.list_divisor;
-  if (a.list_threshold < 1) a.list_threshold = 1;
+  a.list_threshold = tu.list_divisor == 0xFFFFFFFFu ? 0 : std::max<uint64_t>(1, (uint64_t)g->n / tu.list_divisor);
+  a.list_threshold = std::min<uint64_t>(a.list_threshold, geo.lcap);
   a.tlimit = g->tick_khz * 1000ull * 20ull;  // 20 s per barrier wait
+  a.segcap = geo.segcap;
+  a.hcap = geo.hcap;
+  a.lcap = geo.lcap;
+  a.n_src = n_src;
   a.rule = p.rule;
   a.G = G;
+  a.nteams = nteams;
   a.chunk_edges = tu.chunk_edges;
   a.sample_cap = tu.sample_cap;
   a.probe_cap = tu.probe_cap;
   a.filter = tu.no_filter ? 0u : 1u;
-  if (tu.list_divisor == 0xFFFFFFFFu) a.list_threshold = 0;
+  a.snapshot = (p.flags & SSSP_SOLVE_SNAPSHOT_KEYS) ? 1u : 0u;
 
   hipEvent_t ev0, ev1;
   SSSP_HIP_TRY(hipEventCreate(&ev0));
   SSSP_HIP_TRY(hipEventCreate(&ev1));
-  sssp_status rc = SSSP_OK;
-  std::string msg;
-  Control hc;
-  double ms_total = 0;
-  for (int32_t i = 0; i < n_src && rc == SSSP_OK; ++i) {
-    a.source = sources[i];
-    a.dist_out = (decltype(a.dist_out))(dist + (size_t)i * (size_t)g->n);
-    a.dist = g->relabelled ? (decltype(a.dist))g->dist_int.p : a.dist_out;
-    a.xcount = (decltype(a.xcount))(p.extract_counts ? p.extract_counts + (size_t)i * (size_t)g->n : nullptr);
-    a.trace = (decltype(a.trace))(i == 0 ? p.trace : nullptr);
-    a.trace_cap = i == 0 ? p.trace_capacity : 0;
-    reset_control_kernel<<<1, 256, 0, st>>>((Control*)g->ctl.p);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipEventRecord(ev0, st);
-    if (e == hipSuccess) {
-      std::memcpy(g->hargs, &a, sizeof(KArgs));
-      e = hipMemcpyAsync(g->args.p, g->hargs, sizeof(KArgs), hipMemcpyHostToDevice, st);
-    }
-    if (e == hipSuccess) {
-      const KArgs* dargs = (const KArgs*)g->args.p;
-      void* kargs[] = {(void*)&dargs};
-      e = hipLaunchCooperativeKernel((const void*)stepping_kernel, dim3(G), dim3(WG), kargs, 0, st);
-    }
-    if (e == hipSuccess) e = hipEventRecord(ev1, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(&hc, g->ctl.p, sizeof(Control), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) {
-      rc = from_hip(e);
-      msg = std::string("solve: ") + hipGetErrorString(e);
-      break;
-    }
-    float ms = 0;
-    if (hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess) ms_total += ms;
-    if (hc.abort_flag) {
-      rc = SSSP_ERR_DEVICE;
-      msg = "grid barrier timed out (workgroups not co-resident?)";
-      break;
-    }
-    if (hc.status == ST_STEP_LIMIT) {
-      rc = SSSP_ERR_STEP_LIMIT;
-      msg = "max_steps reached with a non-empty queue";
-    }
-    if (stats) {
-      stats->steps += hc.st_steps;
-      stats->extracted += hc.st_extracted;
-      stats->edges_relaxed += hc.st_edges;
-      stats->writemin_success += hc.st_success;
-      stats->dense_steps += hc.st_dense;
-      stats->sampled_steps += hc.st_sampled;
-      for (int k = 0; k < 4; ++k) stats->phase_ms[k] += (double)hc.phase_ticks[k] / (double)g->tick_khz;
-      stats->relax_wg_ms[0] += (double)hc.relax_busy_max / (double)g->tick_khz;
-      stats->relax_wg_ms[1] += (double)hc.relax_busy_sum / (double)G / (double)g->tick_khz;
-    }
+  std::memcpy(g->hargs, &a, sizeof(KArgs));
+  const uint64_t cw = control_words(nteams);
+  hipError_t e = hipMemcpyAsync(g->srcs.p, sources, (size_t)n_src * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(g->args.p, g->hargs, sizeof(KArgs), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    reset_control_kernel<<<64, 256, 0, st>>>((ull*)g->ctl.p, cw);
+    e = hipGetLastError();
   }
+  if (e == hipSuccess) e = hipEventRecord(ev0, st);
+  if (e == hipSuccess) {
+    const KArgs* dargs = (const KArgs*)g->args.p;
+    void* kargs[] = {(void*)&dargs};
+    e = hipLaunchCooperativeKernel((const void*)stepping_kernel, dim3(G), dim3(WG), kargs, 0, st);
+  }
+  if (e == hipSuccess) e = hipEventRecord(ev1, st);
+  GridCtl hg;
+  std::string hteams((size_t)nteams * sizeof(TeamCtl), '\0');
+  if (e == hipSuccess) e = hipMemcpyAsync(&hg, g->ctl.p, sizeof(GridCtl), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&hteams[0], (char*)g->ctl.p + sizeof(GridCtl), hteams.size(), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  float ms = 0;
+  if (e == hipSuccess) (void)hipEventElapsedTime(&ms, ev0, ev1);
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
-  if (stats) stats->device_ms = ms_total;
-  if (rc != SSSP_OK) return fail(rc, msg);
+  if (e != hipSuccess) return fail(from_hip(e), std::string("solve: ") + hipGetErrorString(e));
+  if (hg.abort_flag) return fail(SSSP_ERR_DEVICE, "grid barrier timed out (workgroups not co-resident?)");
+  bool step_limit = false;
+  for (uint32_t t = 0; t < nteams; ++t) {
+    TeamCtl tc;
+    std::memcpy(&tc, &hteams[(size_t)t * sizeof(TeamCtl)], sizeof(TeamCtl));
+    step_limit |= (tc.status & ST_STEP_LIMIT) != 0;
+    if (stats) {
+      stats->steps += tc.st_steps;
+      stats->extracted += tc.st_extracted;
+      stats->edges_relaxed += tc.st_edges;
+      stats->writemin_success += tc.st_success;
+      stats->dense_steps += tc.st_dense;
+      stats->sampled_steps += tc.st_sampled;
+      if (t == 0) {
+        for (int k = 0; k < 4; ++k) stats->phase_ms[k] = (double)tc.phase_ticks[k] / (double)g->tick_khz;
+        stats->relax_wg_ms[0] = (double)tc.relax_busy_max / (double)g->tick_khz;
+        stats->relax_wg_ms[1] = (double)tc.relax_busy_sum / (double)geo.T / (double)g->tick_khz;
+      }
+    }
+  }
+  if (stats) {
+    stats->device_ms = ms;
+    stats->teams = nteams;
+  }
+  if (step_limit) return fail(SSSP_ERR_STEP_LIMIT, "max_steps reached with a non-empty queue");
   return SSSP_OK;
 }
 

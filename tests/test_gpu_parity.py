@@ -71,6 +71,9 @@ def test_tiny_random_graphs_all_rules(sp):
         for rule, kw in RULES:
             dist, _ = sp.solve(G, [s], rule=rule, seed=i, **kw)
             assert_same(sp.to_numpy_u64(dist)[0], exp, f"graph {i} n={g.n} m={g.m} rule {rule} {kw}")
+            if i % 4 == 0:
+                dist, _ = sp.solve(G, [s], rule=rule, seed=i, snapshot_keys=True, **kw)
+                assert_same(sp.to_numpy_u64(dist)[0], exp, f"graph {i} rule {rule} {kw} snapshot keys")
         G.close()
 
 
@@ -292,6 +295,88 @@ def test_step_limit_and_bad_params(sp):
         assert ei.value.status == 1
     with pytest.raises(sp.SSSPError):
         sp.solve(G, [50])
+    G.close()
+
+
+def test_batched_teams_match_oracle(sp):
+    """Many sources in one launch, for team counts that put each team inside
+    one XCD (multiples of 8) and counts that do not (1 and 2)."""
+    g = graphgen.rmat(13, 16, seed=21)
+    rng = np.random.default_rng(21)
+    srcs = [int(x) for x in rng.integers(0, g.n, 37)] + [0, 0]
+    exp = {s: ref(g, s) for s in set(srcs)}
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+    for teams in (0, 1, 2, 8, 16, 64, 256):
+        for rule, kw in [("rho", {"rho": 300}), ("delta", {"delta": 40000}), ("bf", {})]:
+            dist, st = sp.solve(G, srcs, rule=rule, tuning=dict(teams=teams), **kw)
+            got = sp.to_numpy_u64(dist)
+            for i, s in enumerate(srcs):
+                assert_same(got[i], exp[s], f"teams {teams} rule {rule} row {i} source {s}")
+            assert st["teams"] == (teams or 64)
+    G.close()
+
+
+def test_batched_counts_equal_sum_of_single_solves(sp):
+    """With snapshot keys, Relax uses the key each vertex was extracted with,
+    so for rules whose thresholds do not depend on sampling (Delta*,
+    Bellman-Ford, theta = min) each solve extracts the same sets whether its
+    source runs alone or among
+    others: step, extraction and relaxation totals of a batch are the sums
+    over single solves, and the first source's trace is the same record for
+    record (apart from the count of successful WriteMins, which depends on
+    the order in which concurrent WriteMins land)."""
+    g = graphgen.road(60, 60, seed=22)
+    srcs = [0, 3599, 1234, 77, 2500, 999, 42, 3000, 1800, 5]
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+    for rule, kw in [("delta", {"delta": 2500}), ("bf", {}), ("min", {})]:
+        tot = {"steps": 0, "extracted": 0, "edges_relaxed": 0}
+        for s in srcs:
+            _, st = sp.solve(G, [s], rule=rule, snapshot_keys=True, **kw)
+            for k in tot:
+                tot[k] += st[k]
+        _, single = sp.solve(G, srcs[:1], rule=rule, trace=4096, snapshot_keys=True, **kw)
+        for teams in (8, 16, 2):
+            dist, st = sp.solve(G, srcs, rule=rule, tuning=dict(teams=teams), trace=4096,
+                                extract_counts=True, snapshot_keys=True, **kw)
+            for k in tot:
+                assert st[k] == tot[k], (rule, teams, k)
+            strip = lambda recs: [{k: v for k, v in r.items() if k != "successes"} for r in recs]
+            assert strip(st["trace"][:single["steps"]]) == strip(single["trace"]), (rule, teams)
+            counts = st["extract_counts"].cpu().numpy()
+            assert counts.sum() == st["extracted"]
+            got = sp.to_numpy_u64(dist)
+            for i, s in enumerate(srcs):
+                assert_same(got[i], ref(g, s), f"{rule} teams {teams} row {i}")
+                if rule == "min":  # theta = min settles each reachable vertex exactly once
+                    assert np.array_equal(counts[i], (got[i] != INF).astype(np.int32)), (teams, i)
+    G.close()
+
+
+def test_batched_knn_many_queries(sp):
+    """The query workload: a kNN graph kept in the caller's vertex order and 64
+    sources solved in one launch, auto team count."""
+    w = graphgen.workload("knn10", sources=64)
+    g = w.graph
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights, reorder=False)
+    dist, st = sp.solve(G, w.sources, rule="rho", rho=1 << 12)
+    got = sp.to_numpy_u64(dist)
+    assert st["teams"] == 64
+    for i, s in enumerate(w.sources):
+        assert_same(got[i], ref(g, s), f"knn row {i}")
+    # Same answers one source at a time.
+    for i in (0, 31, 63):
+        d1, _ = sp.solve(G, w.sources[i:i + 1], rule="rho", rho=1 << 12)
+        assert_same(sp.to_numpy_u64(d1)[0], got[i], f"knn single {i}")
+    G.close()
+
+
+def test_bad_team_counts_rejected(sp):
+    g = graphgen.from_arcs(10, np.arange(9), np.arange(1, 10), np.ones(9))
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+    for teams in (3, 1 << 20):
+        with pytest.raises(sp.SSSPError) as ei:
+            sp.solve(G, [0, 1], tuning=dict(teams=teams))
+        assert ei.value.status == 1 and "teams" in str(ei.value)
     G.close()
 
 
