@@ -29,6 +29,7 @@
 #include <parallel/algorithm>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstdint>
@@ -464,7 +465,7 @@ int gg_pick_sources(int64_t n, const uint8_t* mask, uint64_t seed, int32_t count
 // Gaussian-mixture point cloud: `clusters` centres ~ U[0,1]^3, `per_cluster`
 // points each ~ N(centre, sigma^2 I) (Box-Muller), not clipped. Exact k nearest
 // neighbours (Euclidean, self excluded, ties broken by smaller index) via a
-// uniform-grid search, union-symmetrised; weight = max(1, llround(wscale * d)).
+// k-d tree search, union-symmetrised; weight = max(1, llround(wscale * d)).
 int gg_knn(int64_t clusters, int64_t per_cluster, double sigma, int k, double wscale, uint64_t seed, gg_csr* out) {
   if (clusters < 1 || per_cluster < 1 || k < 1 || !out) return 1;
   const int64_t n = clusters * per_cluster;
@@ -484,86 +485,120 @@ int gg_knn(int64_t clusters, int64_t per_cluster, double sigma, int k, double ws
       P[3 * i + d] = cx[3 * cl + d] + sigma * z;
     }
   }
-  // Uniform grid over the bounding box, cell side chosen for ~2 points/cell.
-  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-  for (int64_t i = 0; i < n; ++i)
-    for (int d = 0; d < 3; ++d) {
-      lo[d] = std::min(lo[d], P[3 * i + d]);
-      hi[d] = std::max(hi[d], P[3 * i + d]);
-    }
-  const double vol = (hi[0] - lo[0] + 1e-9) * (hi[1] - lo[1] + 1e-9) * (hi[2] - lo[2] + 1e-9);
-  double cell = std::cbrt(vol * 2.0 / (double)n);
-  int64_t G[3];
-  for (int d = 0; d < 3; ++d) G[d] = std::max<int64_t>(1, (int64_t)((hi[d] - lo[d]) / cell) + 1);
-  while (G[0] * G[1] * G[2] > 4 * n + 64) {
-    cell *= 1.25;
-    for (int d = 0; d < 3; ++d) G[d] = std::max<int64_t>(1, (int64_t)((hi[d] - lo[d]) / cell) + 1);
-  }
-  const int64_t ncell = G[0] * G[1] * G[2];
-  auto cell_of = [&](int64_t i, int64_t c[3]) {
-    for (int d = 0; d < 3; ++d) c[d] = std::min<int64_t>(G[d] - 1, (int64_t)((P[3 * i + d] - lo[d]) / cell));
+  // k-d tree over the points: node j (root 1, children 2j and 2j+1) covers
+  // tree positions [lo, hi) and splits them at mid = (lo + hi) / 2 on the axis
+  // of widest extent; positions below mid hold keys <= the split key, those
+  // from mid on hold keys >= it (key = (coordinate, point index)).
+  constexpr int64_t LEAF = 16;
+  std::vector<int32_t> order(n);
+  for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)i;
+  int64_t nodes = 1;
+  while (n / nodes > LEAF) nodes *= 2;
+  std::vector<int8_t> axis_of(2 * nodes, -1);
+  std::vector<double> split_of(2 * nodes, 0.0);
+  struct Range {
+    int64_t node, lo, hi;
   };
-  std::vector<int64_t> cstart(ncell + 1, 0);
-  std::vector<int64_t> cid(n);
-  for (int64_t i = 0; i < n; ++i) {
-    int64_t c[3];
-    cell_of(i, c);
-    cid[i] = (c[2] * G[1] + c[1]) * G[0] + c[0];
-    ++cstart[cid[i] + 1];
+  std::vector<Range> level{{1, 0, n}};
+  while (!level.empty()) {
+    std::vector<Range> next;
+    std::vector<std::array<Range, 2>> kids(level.size());
+    std::vector<char> split(level.size(), 0);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < (int64_t)level.size(); ++r) {
+      const Range R = level[r];
+      if (R.hi - R.lo <= LEAF || 2 * R.node + 1 >= 2 * nodes) continue;
+      double lo3[3] = {1e300, 1e300, 1e300}, hi3[3] = {-1e300, -1e300, -1e300};
+      for (int64_t q = R.lo; q < R.hi; ++q)
+        for (int d = 0; d < 3; ++d) {
+          lo3[d] = std::min(lo3[d], P[3 * (int64_t)order[q] + d]);
+          hi3[d] = std::max(hi3[d], P[3 * (int64_t)order[q] + d]);
+        }
+      int ax = 0;
+      for (int d = 1; d < 3; ++d)
+        if (hi3[d] - lo3[d] > hi3[ax] - lo3[ax]) ax = d;
+      const int64_t mid = (R.lo + R.hi) / 2;
+      std::nth_element(order.begin() + R.lo, order.begin() + mid, order.begin() + R.hi, [&](int32_t a, int32_t b) {
+        const double pa = P[3 * (int64_t)a + ax], pb = P[3 * (int64_t)b + ax];
+        return pa < pb || (pa == pb && a < b);
+      });
+      axis_of[R.node] = (int8_t)ax;
+      split_of[R.node] = P[3 * (int64_t)order[mid] + ax];
+      kids[r] = {Range{2 * R.node, R.lo, mid}, Range{2 * R.node + 1, mid, R.hi}};
+      split[r] = 1;
+    }
+    for (size_t r = 0; r < level.size(); ++r)
+      if (split[r]) {
+        next.push_back(kids[r][0]);
+        next.push_back(kids[r][1]);
+      }
+    level.swap(next);
   }
-  for (int64_t c = 0; c < ncell; ++c) cstart[c + 1] += cstart[c];
-  std::vector<int32_t> cpts(n);
-  {
-    std::vector<int64_t> cur(cstart.begin(), cstart.end() - 1);
-    for (int64_t i = 0; i < n; ++i) cpts[cur[cid[i]]++] = (int32_t)i;
-  }
+  // Points in tree order, for locality of the leaf scans.
+  std::vector<double> T((size_t)n * 3);
+  for (int64_t q = 0; q < n; ++q)
+    for (int d = 0; d < 3; ++d) T[3 * q + d] = P[3 * (int64_t)order[q] + d];
+
   std::vector<int32_t> nbr((size_t)n * k);
-  std::atomic<int> fail{0};
 #pragma omp parallel
   {
-    std::vector<std::pair<double, int32_t>> cand;
-#pragma omp for schedule(dynamic, 512)
+    // The k best (squared distance, index) pairs so far, ascending.
+    std::vector<std::pair<double, int32_t>> best;
+    struct Frame {
+      int64_t node, lo, hi;
+      double bound;  // lower bound on the squared distance to any point in the node
+    };
+    std::vector<Frame> stack;
+#pragma omp for schedule(dynamic, 1024)
     for (int64_t i = 0; i < n; ++i) {
-      int64_t c[3];
-      cell_of(i, c);
-      // Grow the searched cube of cells until the k-th best distance is
-      // certified: every unsearched point lies farther than r * cell.
-      for (int64_t r = 1;; ++r) {
-        cand.clear();
-        for (int64_t z = std::max<int64_t>(0, c[2] - r); z <= std::min<int64_t>(G[2] - 1, c[2] + r); ++z)
-          for (int64_t y = std::max<int64_t>(0, c[1] - r); y <= std::min<int64_t>(G[1] - 1, c[1] + r); ++y)
-            for (int64_t x = std::max<int64_t>(0, c[0] - r); x <= std::min<int64_t>(G[0] - 1, c[0] + r); ++x) {
-              const int64_t cc = (z * G[1] + y) * G[0] + x;
-              for (int64_t q = cstart[cc]; q < cstart[cc + 1]; ++q) {
-                const int32_t j = cpts[q];
-                if (j == i) continue;
-                double s = 0;
-                for (int d = 0; d < 3; ++d) {
-                  const double t = P[3 * i + d] - P[3 * (int64_t)j + d];
-                  s += t * t;
-                }
-                cand.push_back({s, j});
-              }
+      const double* pi = &P[3 * i];
+      best.clear();
+      stack.clear();
+      stack.push_back({1, 0, n, 0.0});
+      while (!stack.empty()) {
+        const Frame f = stack.back();
+        stack.pop_back();
+        // Prune only on a strictly larger bound, so that points at the k-th
+        // distance are still seen and the smaller index wins the tie.
+        if ((int64_t)best.size() == k && f.bound > best.back().first) continue;
+        const int ax = f.node < 2 * nodes ? axis_of[f.node] : -1;
+        if (ax < 0) {
+          for (int64_t q = f.lo; q < f.hi; ++q) {
+            const int32_t j = order[q];
+            if (j == i) continue;
+            double s = 0;
+            for (int d = 0; d < 3; ++d) {
+              const double t = pi[d] - T[3 * q + d];
+              s += t * t;
             }
-        const bool whole = c[0] - r <= 0 && c[1] - r <= 0 && c[2] - r <= 0 && c[0] + r >= G[0] - 1 &&
-                           c[1] + r >= G[1] - 1 && c[2] + r >= G[2] - 1;
-        if ((int64_t)cand.size() >= k) {
-          std::nth_element(cand.begin(), cand.begin() + (k - 1), cand.end());
-          const double kth = cand[k - 1].first;
-          const double reach = (double)r * cell;
-          if (whole || kth <= reach * reach) {
-            std::sort(cand.begin(), cand.end());
-            for (int q = 0; q < k; ++q) nbr[(size_t)i * k + q] = cand[q].second;
-            break;
+            const std::pair<double, int32_t> c{s, j};
+            if ((int64_t)best.size() == k) {
+              if (!(c < best.back())) continue;
+              best.pop_back();
+            }
+            best.insert(std::upper_bound(best.begin(), best.end(), c), c);
           }
-        } else if (whole) {
-          fail.store(1);
-          break;
+          continue;
+        }
+        const int64_t mid = (f.lo + f.hi) / 2;
+        const double sp = split_of[f.node];
+        // The far side's points lie beyond the split plane: its squared
+        // distance from the query bounds theirs from below (rounding is
+        // monotone, so the bound also holds for the computed distances).
+        const double gap = pi[ax] < sp ? sp - pi[ax] : pi[ax] - sp;
+        const Frame lo_f{2 * f.node, f.lo, mid, pi[ax] < sp ? f.bound : std::max(f.bound, gap * gap)};
+        const Frame hi_f{2 * f.node + 1, mid, f.hi, pi[ax] < sp ? std::max(f.bound, gap * gap) : f.bound};
+        if (pi[ax] < sp) {
+          stack.push_back(hi_f);
+          stack.push_back(lo_f);
+        } else {
+          stack.push_back(lo_f);
+          stack.push_back(hi_f);
         }
       }
+      for (int q = 0; q < k; ++q) nbr[(size_t)i * k + q] = best[q].second;
     }
   }
-  if (fail.load()) return 3;
   std::vector<Arc> pairs((size_t)n * k);
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i)

@@ -162,6 +162,9 @@ typedef struct {
    * slowest workgroup's Relax time, [1] the mean workgroup's Relax time. */
   double relax_wg_ms[2];
   uint64_t teams;            /* teams the grid was split into */
+  uint64_t queue_dense;      /* sum of |Q| over steps whose Extract scanned the bitmap */
+  uint64_t queue_list;       /* sum of |Q| over steps whose Extract read the explicit list */
+  uint64_t list_appends;     /* entries written to explicit lists (kept and new members) */
 } sssp_stats;
 
 typedef struct sssp_graph sssp_graph; /* opaque */

@@ -71,7 +71,8 @@ class sssp_stats(ctypes.Structure):
                 ("writemin_success", ctypes.c_uint64), ("dense_steps", ctypes.c_uint64),
                 ("sampled_steps", ctypes.c_uint64), ("device_ms", ctypes.c_double),
                 ("phase_ms", ctypes.c_double * 4), ("relax_wg_ms", ctypes.c_double * 2),
-                ("teams", ctypes.c_uint64)]
+                ("teams", ctypes.c_uint64), ("queue_dense", ctypes.c_uint64), ("queue_list", ctypes.c_uint64),
+                ("list_appends", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}

@@ -102,6 +102,7 @@ struct TeamCtl {
   ull query;   // index of the source being solved
   ull status;  // 1: step limit reached on some query
   ull st_steps, st_extracted, st_edges, st_success, st_dense, st_sampled;
+  ull st_qdense, st_qlist, st_appends;
   ull relax_busy_max, relax_busy_sum;
   ull phase_ticks[4];  // init, threshold, extract, relax (the team's first workgroup)
   alignas(128) StepSlot slot[3];
@@ -889,6 +890,12 @@ __device__ __noinline__ void step_bookkeeping(const KArgs& a, StepSlot* S, ull t
     tc->st_success += s;
     tc->st_dense += (flags & 1u) ? 1 : 0;
     tc->st_sampled += (flags & 4u) ? 1 : 0;
+    if (flags & 1u) {
+      tc->st_qdense += q;
+    } else {
+      tc->st_qlist += q;
+    }
+    if (flags & 2u) tc->st_appends += ld_agent(&S->list_next);
     tc->relax_busy_max += ~negbusy;
     tc->relax_busy_sum += busy;
     if (a.trace && tc->query == 0 && t < a.trace_cap) {
@@ -1142,8 +1149,8 @@ struct Geometry {
   uint64_t nwords, segcap, hcap, lcap;
 };
 
-constexpr uint64_t TEAM_SEGMENT_CAP = 1ull << 20;  // F entries per workgroup when teams share the grid
-constexpr uint64_t TEAM_LIST_CAP = 1ull << 22;     // explicit-list entries per team when teams share the grid
+constexpr uint64_t TEAM_SEGMENT_CAP = 1ull << 16;  // F entries per workgroup when teams share the grid
+constexpr uint64_t TEAM_LIST_CAP = 1ull << 20;     // explicit-list entries per team when teams share the grid
 
 Geometry make_geometry(const sssp_graph* g, const sssp_tuning& tu, uint32_t G, uint32_t nteams) {
   Geometry geo;
@@ -1355,6 +1362,9 @@ sssp_status sssp_solve(const sssp_graph* gc, const int32_t* sources, int32_t n_s
       stats->writemin_success += tc.st_success;
       stats->dense_steps += tc.st_dense;
       stats->sampled_steps += tc.st_sampled;
+      stats->queue_dense += tc.st_qdense;
+      stats->queue_list += tc.st_qlist;
+      stats->list_appends += tc.st_appends;
       if (t == 0) {
         for (int k = 0; k < 4; ++k) stats->phase_ms[k] = (double)tc.phase_ticks[k] / (double)g->tick_khz;
         stats->relax_wg_ms[0] = (double)tc.relax_busy_max / (double)g->tick_khz;
