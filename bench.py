@@ -47,7 +47,7 @@ WORKLOADS = {
     "grid256": "256x256 4-neighbour grid, w ~ U[1, 2^16), source 0; rho-stepping rho=4096",
     "knn10000": "10-NN graph of 10^7 points: 1000 Gaussian clusters (sigma 0.01) of 10^4 points in the unit "
                 "cube, union-symmetrised, w = max(1, llround(1e6 * dist)), caller vertex order kept; 64 sources "
-                "uniform over all vertices, solved together in one launch; rho-stepping",
+                "uniform over all vertices, solved together in one launch; rule and parameters autotuned",
 }
 BATCHED = {"knn10000": 64}
 
@@ -208,14 +208,36 @@ def run_batched(args, torch, sp, w):
     g = w.graph
     srcs = [int(x) for x in w.sources]
     nq = len(srcs)
+    from paper_2105_06145_amd import autotune as at
     G = sp.Graph.from_csr(g.offsets, g.targets, g.weights, reorder=False)
     torch.cuda.synchronize()
-    rho = args.rho or int(w.params["rho"])
     out = torch.empty((nq, g.n), dtype=torch.int64, device="cuda")
     one = torch.empty((1, g.n), dtype=torch.int64, device="cuda")
+
+    def call(cfg, sources, dst, extra_tuning=None):
+        tun = {**(cfg.get("tuning") or {}), **(extra_tuning or {})}
+        kw = {k: cfg[k] for k in ("rho", "delta") if k in cfg}
+        return sp.solve(G, sources, rule=cfg["rule"], tuning=tun or None, out=dst, **kw)
+
+    default = {"rule": "rho", "rho": args.rho or int(w.params["rho"])}
+    if args.tune_budget > 0:
+        # Batched: the parameter search times the whole batch. Plain: it times
+        # the first 8 queries one launch each, with one whole-grid team.
+        t0 = time.time()
+        cfg_b = at.Tuner(budget_s=args.tune_budget).tune(G, srcs)
+        log(f"autotune batched ({time.time() - t0:.1f}s): {cfg_b}")
+
+        def plain_measure(cfg):
+            return sum(call(cfg, [s], one, {"teams": 1})[1]["device_ms"] for s in srcs[:8])
+        t0 = time.time()
+        w_med = G.summary["weight_q10_50_90"][1] or 1
+        cfg_p = at.Tuner(budget_s=args.tune_budget, measure=plain_measure).search(G.n, 1, w_med)
+        log(f"autotune plain ({time.time() - t0:.1f}s): {cfg_p}")
+    else:
+        cfg_b = cfg_p = default
     for _ in range(args.warmup):
-        sp.solve(G, srcs, rule="rho", rho=rho, out=out)
-    sp.solve(G, srcs[:1], rule="rho", rho=rho, out=one, tuning=dict(teams=1))
+        call(cfg_b, srcs, out)
+    call(cfg_p, srcs[:1], one, {"teams": 1})
 
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -223,7 +245,7 @@ def run_batched(args, torch, sp, w):
     edges = kernel_ms = b_alg = 0
     ev0.record()
     for _ in range(args.steps):
-        _, st = sp.solve(G, srcs, rule="rho", rho=rho, out=out)
+        _, st = call(cfg_b, srcs, out)
         edges += st["edges_relaxed"]
         kernel_ms += st["device_ms"]
         b_alg += algorithmic_bytes(g.n, st, nq, relabelled=False)
@@ -240,7 +262,7 @@ def run_batched(args, torch, sp, w):
     lat = []
     ev0.record()
     for s in srcs:
-        _, st1 = sp.solve(G, [s], rule="rho", rho=rho, out=one, tuning=dict(teams=1))
+        _, st1 = call(cfg_p, [s], one, {"teams": 1})
         plain_edges += st1["edges_relaxed"]
         lat.append(st1["device_ms"])
     ev1.record()
@@ -261,12 +283,14 @@ def run_batched(args, torch, sp, w):
                "sample": f"the same {nq} queries, one binary-heap Dijkstra each ({scanned_total} arcs relaxed, "
                          f"{secs:.2f} s, 1 thread, {nq / secs:.2f} queries/s)"}
 
-    config = {"workload": WORKLOADS[args.workload], "n": g.n, "m": g.m, "queries": nq, "rule": "rho", "rho": rho,
-              "teams": teams, "edges_relaxed_per_batch": int(edges // args.steps), "useful_arcs": m_reach}
+    strip = lambda c: {k: v for k, v in c.items() if k in ("rule", "rho", "delta", "tuning")}
+    config = {"workload": WORKLOADS[args.workload], "n": g.n, "m": g.m, "queries": nq, **strip(cfg_b),
+              "teams": teams, "edges_relaxed_per_batch": int(edges // args.steps), "useful_arcs": m_reach,
+              "tuned": args.tune_budget > 0}
     res = base_record(args, edges / (total_ms * 1e6), ms_per, config, roofline, cpu)
     res["gteps_useful"] = round(m_reach * args.steps / (total_ms * 1e6), 4)
     res["queries_per_s"] = round(nq * args.steps / (total_ms * 1e-3), 1)
-    res["plain"] = {"what": f"the same {nq} queries, one launch each, whole grid per query",
+    res["plain"] = {"what": f"the same {nq} queries, one launch each, whole grid per query", "config": strip(cfg_p),
                     "total_ms": round(plain_ms, 3), "queries_per_s": round(nq / (plain_ms * 1e-3), 1),
                     "gteps": round(plain_edges / (plain_ms * 1e6), 4),
                     "gteps_useful": round(m_reach / (plain_ms * 1e6), 4),
@@ -288,6 +312,8 @@ def main():
     ap.add_argument("--sweep", default="", metavar="LOG2_LIST",
                     help="e.g. 16,17,18,19,20,21,22: time 3 solves per rho first and use the fastest")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-budget", type=float, default=20.0,
+                    help="seconds of parameter search per mode for the batched workload (0 = workload defaults)")
     ap.add_argument("--cpu-settle-cap", type=int, default=0,
                     help="stop the CPU oracle after this many settled vertices (0 = full solve)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

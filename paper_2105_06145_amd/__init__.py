@@ -50,13 +50,51 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _summary(deg, w, reorder: bool) -> dict:
+    """Shape summary of a graph for parameter caching: sizes, the log2
+    histogram of out-degrees and weight quantiles (numpy or torch inputs)."""
+    if hasattr(deg, "cpu"):
+        torch = _torch()
+        lg = torch.log2(deg.clamp(min=1).double()).floor().long().clamp(max=40)
+        hist = torch.bincount(lg, minlength=41).cpu().numpy()
+        hist[0] -= int((deg == 0).sum().item())
+        zero = int((deg == 0).sum().item())
+        ws = w.long() & 0xFFFFFFFF
+        if ws.numel() > (1 << 20):
+            ws = ws[:: ws.numel() // (1 << 20)]
+        q = torch.quantile(ws.double(), torch.tensor([0.1, 0.5, 0.9], dtype=torch.float64, device=ws.device)) \
+            if ws.numel() else torch.zeros(3, dtype=torch.float64)
+        quant = [int(x) for x in q.cpu().numpy()]
+    else:
+        zero = int((deg == 0).sum())
+        hist = np.bincount(np.floor(np.log2(np.maximum(deg, 1))).astype(np.int64).clip(max=40), minlength=41)
+        hist[0] -= zero
+        ws = np.asarray(w, dtype=np.uint32)
+        if ws.size > (1 << 20):
+            ws = ws[:: ws.size // (1 << 20)]
+        quant = [int(x) for x in np.quantile(ws.astype(np.float64), [0.1, 0.5, 0.9])] if ws.size else [0, 0, 0]
+    hist = [int(x) for x in hist]
+    while hist and hist[-1] == 0:
+        hist.pop()
+    return {"zero_degree": zero, "degree_log2_hist": hist, "weight_q10_50_90": quant, "reorder": bool(reorder)}
+
+
 class Graph:
     """A CSR graph resident on the current GPU (owned by the library)."""
 
-    def __init__(self, handle, n: int, m: int):
+    def __init__(self, handle, n: int, m: int, summary: dict | None = None):
         self._h = handle
         self.n = n
         self.m = m
+        self.summary = {"n": n, "m": m, **(summary or {})}
+
+    @property
+    def fingerprint(self) -> str:
+        """Stable hash of the graph's shape summary (sizes, degree histogram,
+        weight quantiles, vertex order): graphs that share it are tuned alike."""
+        import hashlib
+        import json
+        return hashlib.sha1(json.dumps(self.summary, sort_keys=True).encode()).hexdigest()[:16]
 
     @classmethod
     def from_csr(cls, offsets, targets, weights, validate: bool = True, reorder: bool = True,
@@ -75,6 +113,7 @@ class Graph:
                     weights.dtype not in (torch.int32, torch.uint32):
                 raise ValueError("dtypes: offsets int32/int64, targets int32, weights uint32 (or int32 bits)")
             offsets, targets, weights = offsets.contiguous(), targets.contiguous(), weights.contiguous()
+            summary = _summary(offsets[1:].long() - offsets[:-1].long(), weights, reorder)
             n = offsets.numel() - 1
             m = targets.numel()
             ptrs = [ctypes.c_void_p(t.data_ptr()) for t in (offsets, targets, weights)]
@@ -87,6 +126,7 @@ class Graph:
             ow = N.SSSP_OFFSETS_I64 if off.dtype == np.int64 else N.SSSP_OFFSETS_I32
             tgt = np.ascontiguousarray(targets, dtype=np.int32)
             w = np.ascontiguousarray(weights, dtype=np.uint32)
+            summary = _summary(np.diff(off.astype(np.int64)), w, reorder)
             n = off.shape[0] - 1
             m = tgt.shape[0]
             ptrs = [ctypes.c_void_p(a.ctypes.data) for a in (off, tgt, w)]
@@ -96,7 +136,7 @@ class Graph:
         del keep
         if rc != N.SSSP_OK:
             raise SSSPError(rc, "sssp_graph_create")
-        return cls(h, n, m)
+        return cls(h, n, m, summary)
 
     def device_bytes(self) -> int:
         rc, _, _, b = sssp_graph_info(self._h)

@@ -1,0 +1,189 @@
+"""Per-graph parameter search for the stepping solver.
+
+The stepping rules reach the same distances for every parameter (Sec. 3.2,
+Table 2); rho, Delta and the kernel's tuning knobs change only the number of
+steps and the redundant work, and the best values depend on the graph (the
+paper picks rho per graph and motivates a rule that needs no preprocessing).
+This module searches them by timing real solves on the device:
+
+  1. the rule parameter: rho over powers of four from 2^8 up to n, then the
+     neighbouring powers of two; Delta over the median arc weight times
+     powers of four, then the neighbouring powers of two;
+  2. for batches, the number of teams the persistent grid is split into;
+  3. the hub-degree threshold, then the explicit-list switch.
+
+Each candidate is timed `reps` times (median of the kernel time). Results are
+cached per (graph fingerprint, batch-size class) in a JSON file, so a graph
+seen again, or another graph of the same shape summary, is solved with its
+tuned parameters at once.
+"""
+
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+from typing import Callable
+
+
+def batch_class(nsrc: int) -> int:
+    """1 for single solves, else the power of two >= nsrc (min 8)."""
+    if nsrc <= 1:
+        return 1
+    return max(8, 1 << (nsrc - 1).bit_length())
+
+
+def rho_candidates(n: int) -> list[int]:
+    top = max(8, (max(n, 2) - 1).bit_length())
+    return [1 << k for k in range(8, top + 1, 2)]
+
+
+def delta_candidates(w_median: int) -> list[int]:
+    base = max(1, int(w_median))
+    return [max(1, base << k) if k >= 0 else max(1, base >> -k) for k in range(-2, 11, 2)]
+
+
+def team_candidates(nsrc: int, grid: int = 1024) -> list[int]:
+    out, t = [], 8
+    while t <= grid and t < 2 * max(nsrc, 8):
+        out.append(t)
+        t *= 2
+    return out
+
+
+class Tuner:
+    """Coordinate search over (rule parameter, teams, hub_degree, list_divisor).
+
+    `measure(config) -> ms` times one configuration; by default it runs the
+    solver on the given graph and sources. A config is a dict with keys rule,
+    rho or delta, and tuning (a dict of sssp_tuning fields).
+    """
+
+    def __init__(self, cache_path: str | None = None, budget_s: float = 60.0, reps: int = 2,
+                 measure: Callable[[dict], float] | None = None, log: Callable[[str], None] | None = None):
+        self.cache_path = cache_path
+        self.budget_s = budget_s
+        self.reps = reps
+        self._measure = measure
+        self._log = log or (lambda s: None)
+        self.history: list[tuple[dict, float]] = []
+
+    # -- cache ------------------------------------------------------------
+    def _load(self) -> dict:
+        if not self.cache_path or not os.path.exists(self.cache_path):
+            return {}
+        with open(self.cache_path) as f:
+            return json.load(f)
+
+    def _store(self, key: str, value: dict):
+        if not self.cache_path:
+            return
+        d = self._load()
+        d[key] = value
+        tmp = self.cache_path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.cache_path)
+
+    @staticmethod
+    def key(fingerprint: str, nsrc: int) -> str:
+        return f"{fingerprint}/{batch_class(nsrc)}"
+
+    def lookup(self, fingerprint: str, nsrc: int) -> dict | None:
+        return self._load().get(self.key(fingerprint, nsrc))
+
+    # -- search -----------------------------------------------------------
+    def _eval(self, cfg: dict, best: list) -> float:
+        ms = self._measure(cfg)
+        self.history.append((cfg, ms))
+        self._log(f"autotune {json.dumps(cfg, sort_keys=True)}: {ms:.3f} ms")
+        if ms < best[1]:
+            best[0], best[1] = cfg, ms
+        return ms
+
+    def search(self, n: int, nsrc: int, w_median: int, rules=("rho", "delta"), grid: int = 1024) -> dict:
+        t0 = time.monotonic()
+        best = [None, math.inf]
+
+        def out_of_time():
+            return time.monotonic() - t0 > self.budget_s
+
+        def with_tuning(cfg, **kw):
+            c = dict(cfg)
+            c["tuning"] = {**cfg.get("tuning", {}), **kw}
+            return c
+
+        base_tuning = {"teams": 0} if nsrc > 1 else {}
+        # 1. rule parameter: coarse (x4), then the two neighbours (x2).
+        for rule in rules:
+            if rule == "rho":
+                name, cands = "rho", rho_candidates(n)
+            elif rule == "delta":
+                name, cands = "delta", delta_candidates(w_median)
+            else:
+                self._eval({"rule": rule, "tuning": dict(base_tuning)}, best)
+                continue
+            scores = {}
+            for v in cands:
+                if out_of_time() and best[0] is not None:
+                    break
+                scores[v] = self._eval({"rule": rule, name: v, "tuning": dict(base_tuning)}, best)
+            if not scores:
+                continue
+            v0 = min(scores, key=scores.get)
+            for v in (v0 // 2, v0 * 2):
+                if v >= 1 and v not in scores and not out_of_time():
+                    scores[v] = self._eval({"rule": rule, name: v, "tuning": dict(base_tuning)}, best)
+        # 2.-3. kernel knobs, one at a time around the best so far.
+        knobs = []
+        if nsrc > 1:
+            knobs.append(("teams", team_candidates(nsrc, grid)))
+        knobs.append(("hub_degree", [256, 1024, 4096]))
+        knobs.append(("list_divisor", [16, 64, 256]))
+        for knob, values in knobs:
+            start = best[0]
+            for v in values:
+                if out_of_time():
+                    break
+                if start.get("tuning", {}).get(knob) == v:
+                    continue
+                self._eval(with_tuning(start, **{knob: v}), best)
+        cfg = dict(best[0])
+        cfg["ms"] = best[1]
+        cfg["evaluations"] = len(self.history)
+        return cfg
+
+    def tune(self, graph, sources, rules=("rho", "delta"), force: bool = False) -> dict:
+        """Tuned configuration for solving `sources` on `graph` (a Graph):
+        from the cache when present, else searched now and cached."""
+        nsrc = len(sources)
+        fp = graph.fingerprint
+        if not force:
+            hit = self.lookup(fp, nsrc)
+            if hit is not None:
+                return hit
+        if self._measure is None:
+            from . import solve
+
+            def measure(cfg):
+                kw = {k: v for k, v in cfg.items() if k in ("rho", "delta")}
+                times = []
+                for _ in range(self.reps):
+                    _, st = solve(graph, sources, rule=cfg["rule"], tuning=cfg.get("tuning") or None, **kw)
+                    times.append(st["device_ms"])
+                times.sort()
+                return times[len(times) // 2]
+            self._measure = measure
+        w_median = graph.summary.get("weight_q10_50_90", [0, 1, 0])[1] or 1
+        cfg = self.search(graph.n, nsrc, w_median, rules)
+        self._store(self.key(fp, nsrc), cfg)
+        return cfg
+
+
+def solve_tuned(graph, sources, tuner: Tuner, **kw):
+    """Solve with the tuner's configuration for this graph and batch size."""
+    from . import solve
+    cfg = tuner.tune(graph, sources)
+    params = {k: v for k, v in cfg.items() if k in ("rho", "delta")}
+    return solve(graph, sources, rule=cfg["rule"], tuning=cfg.get("tuning") or None, **params, **kw)

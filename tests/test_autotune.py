@@ -1,0 +1,87 @@
+"""Parameter search (host logic on a synthetic cost model) and, on the GPU,
+tuned solves against the oracle."""
+
+import math
+
+import numpy as np
+import pytest
+
+from paper_2105_06145_amd import autotune as at
+
+
+def cost_model(cfg):
+    """A made-up cost with its minimum at rho = 2^14 (or Delta = 4096),
+    teams = 32, hub_degree = 4096, list_divisor = 64."""
+    t = cfg.get("tuning", {})
+    if cfg["rule"] == "rho":
+        c = 10 + (math.log2(cfg["rho"]) - 14) ** 2
+    else:
+        c = 12 + (math.log2(cfg["delta"]) - 12) ** 2
+    teams = t.get("teams", 0) or 64  # 0: the library's choice for 40 sources
+    c += 0 if teams == 32 else 1 + abs(math.log2(teams) - 5)
+    c -= 0.5 if t.get("hub_degree") == 4096 else 0
+    c += 0 if t.get("list_divisor", 64) == 64 else 0.25
+    return c
+
+
+def test_candidates():
+    assert at.rho_candidates(1 << 20) == [1 << k for k in range(8, 21, 2)]
+    assert at.rho_candidates(5) == [256]
+    assert at.delta_candidates(1000) == [250, 1000, 4000, 16000, 64000, 256000, 1024000]
+    assert at.team_candidates(64) == [8, 16, 32, 64]
+    assert at.team_candidates(3) == [8]
+    assert [at.batch_class(x) for x in (1, 2, 8, 9, 64, 65)] == [1, 8, 8, 16, 64, 128]
+
+
+def test_search_finds_the_minimum_of_the_model():
+    tu = at.Tuner(measure=cost_model, budget_s=60)
+    cfg = tu.search(n=1 << 20, nsrc=40, w_median=1000)
+    assert cfg["rule"] == "rho" and cfg["rho"] == 1 << 14
+    assert cfg["tuning"]["teams"] == 32 and cfg["tuning"]["hub_degree"] == 4096
+    assert cfg.get("tuning", {}).get("list_divisor", 64) == 64
+    assert cfg["ms"] == pytest.approx(9.5)
+    assert cfg["evaluations"] == len(tu.history)
+
+
+def test_search_single_source_has_no_teams_and_obeys_budget():
+    tu = at.Tuner(measure=cost_model, budget_s=60)
+    cfg = tu.search(n=1 << 16, nsrc=1, w_median=1 << 12, rules=("delta",))
+    assert cfg["rule"] == "delta" and cfg["delta"] == 1 << 12
+    assert all("teams" not in c.get("tuning", {}) for c, _ in tu.history)
+    tu0 = at.Tuner(measure=cost_model, budget_s=0)
+    cfg0 = tu0.search(n=1 << 16, nsrc=1, w_median=100)
+    assert len(tu0.history) == 1 and cfg0["ms"] == tu0.history[0][1]
+
+
+def test_cache_round_trip(tmp_path):
+    path = str(tmp_path / "tune.json")
+    tu = at.Tuner(cache_path=path, measure=cost_model)
+
+    class FakeGraph:
+        n = 1 << 12
+        fingerprint = "abc"
+        summary = {"weight_q10_50_90": [1, 4096, 9]}
+
+    cfg = tu.tune(FakeGraph(), list(range(10)))
+    again = at.Tuner(cache_path=path, measure=lambda c: pytest.fail("cache miss"))
+    assert again.tune(FakeGraph(), list(range(12))) == cfg  # same batch class (16)
+    assert again.lookup("abc", 1) is None
+
+
+@pytest.mark.gpu
+def test_tuned_solves_match_oracle(torch_cuda, tmp_path):
+    import graphgen
+    import oracle
+    import paper_2105_06145_amd as sp
+    g = graphgen.rmat(12, 16, seed=31)
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+    tu = at.Tuner(cache_path=str(tmp_path / "t.json"), budget_s=20)
+    srcs = [int(np.argmax(g.degrees())), 5, 77, 1000, 4000, 123, 9, 2048, 17]
+    for batch in (srcs[:1], srcs):
+        dist, st = at.solve_tuned(G, batch, tu)
+        got = sp.to_numpy_u64(dist)
+        for i, s in enumerate(batch):
+            exp = oracle.dijkstra(g.offsets, g.targets, g.weights, s)
+            assert np.array_equal(got[i], exp), (len(batch), i)
+    assert tu.lookup(G.fingerprint, 1) is not None and tu.lookup(G.fingerprint, len(srcs)) is not None
+    G.close()
