@@ -197,7 +197,8 @@ sssp_status sssp_graph_create(int64_t n, int64_t m, sssp_offset_width ow, const 
                               sssp_graph** out);
 
 /* Release the graph and its device memory. NULL is accepted. Must not race a
- * solve on the same graph. */
+ * solve on the same graph; refused (INVALID_ARGUMENT) while a server runs on
+ * it. */
 sssp_status sssp_graph_destroy(sssp_graph* g);
 
 /* Query sizes: vertices, arcs and device bytes held (graph plus workspace). */
@@ -221,6 +222,83 @@ sssp_status sssp_graph_info(const sssp_graph* g, int64_t* n, int64_t* m, uint64_
  */
 sssp_status sssp_solve(const sssp_graph* g, const int32_t* sources, int32_t n_src, const sssp_params* params,
                        uint64_t* dist, void* stream, sssp_stats* stats);
+
+/*
+ * Order-independent checksum of a distance row: the sum over v of a 64-bit
+ * mix of (v, dist[v]), modulo 2^64. The mix is the SplitMix64 finaliser
+ * applied to dist[v] XOR (v * 0x9E3779B97F4A7C15). dist is a device pointer
+ * to n entries; the result is written to the host pointer `hash`. Used to
+ * compare served rows with rows solved alone without copying them.
+ */
+sssp_status sssp_row_hash(const uint64_t* dist, int64_t n, void* stream, uint64_t* hash);
+
+/*
+ * Serving: a persistent launch that takes single-source requests from a ring
+ * in host memory while it runs (continuous batching). Its workgroups form
+ * tuning.teams teams (default: teams of 16 workgroups); a free team takes the
+ * next posted request, solves it (Alg. 1) into the caller's row, and marks it
+ * done, so requests join and leave the running batch one by one.
+ *
+ * sssp_server_start launches the kernel and returns at once. The launch runs
+ * on a stream the library creates with a hardware queue of its own (HIP
+ * otherwise shares a few queues among all streams, and a queue runs its
+ * kernels in order, so a persistent launch would hold back unrelated work);
+ * `stream` only orders the start after work already queued on it. HIP's
+ * CU-masked streams are blocking streams: while a server runs, work queued
+ * on the legacy NULL stream waits for it, so keep such work on non-blocking
+ * streams (hipStreamNonBlocking).
+ *   params   rule and parameters as for sssp_solve (trace, extract_counts and
+ *            max_steps must be unset).
+ *   dist_rows device pointer to rows * n uint64 entries; a request names the
+ *            row its distances go to, and holds it until it is polled done
+ *            (rows bound the requests in flight). The caller owns the memory.
+ *   ring_capacity  most requests posted but not yet taken by a team.
+ *   flags    SSSP_SERVE_HASH: also compute each finished row's checksum
+ *            (as sssp_row_hash), returned by sssp_server_poll.
+ *   idle_ms  a team waiting longer than this for a request ends the launch
+ *            (0 = 60000).
+ * tuning.blocks_per_cu sets the grid (default 2 per compute unit, half of the
+ * kernel's occupancy of 4, so that other kernels such as copies still find
+ * room while the server runs). Servers on several graphs may run side by side
+ * on separate streams when their blocks_per_cu sum to at most 4; otherwise
+ * the launch cannot be resident and stops with SSSP_ERR_DEVICE. Kernels
+ * launched meanwhile wait for free slots: with servers holding all of them, a
+ * copy on another stream waits until a server ends. While a server runs,
+ * sssp_solve and another server on the same graph are refused.
+ * One host thread drives a server (submit, poll and stop do not lock).
+ */
+#define SSSP_SERVE_HASH 0x1u
+typedef struct sssp_server sssp_server; /* opaque */
+
+sssp_status sssp_server_start(const sssp_graph* g, const sssp_params* params, uint64_t* dist_rows, uint32_t rows,
+                              uint32_t ring_capacity, uint32_t flags, uint32_t idle_ms, void* stream,
+                              sssp_server** out);
+
+/* Post one request (host call; validated here). *ticket numbers requests in
+ * posting order from 0; the request waits in ring entry ticket % capacity
+ * until a team takes it. INVALID_ARGUMENT when that entry still holds an
+ * untaken request (ring full), the row holds a request not yet polled done,
+ * the server is stopped, or source / row is out of range; DEVICE when the
+ * launch has already ended (its idle limit passed).
+ * A request posted while the last teams are leaving at the idle limit is
+ * never served: callers that let a server idle should poll with a deadline. */
+sssp_status sssp_server_submit(sssp_server* s, int32_t source, uint32_t row, uint64_t* ticket);
+
+/* Collect up to `max` requests finished since the last poll: their tickets
+ * and, with SSSP_SERVE_HASH, their row checksums (hashes may be NULL).
+ * *count receives the number returned. Completion order may differ from
+ * posting order. */
+sssp_status sssp_server_poll(sssp_server* s, uint64_t* tickets, uint64_t* hashes, uint32_t max, uint32_t* count);
+
+/* Close the ring: the kernel finishes every posted request, then ends; waits
+ * for it and fills stats (totals over all requests; device_ms = the launch's
+ * lifetime). Requests finished meanwhile can still be polled. Idempotent. */
+sssp_status sssp_server_stop(sssp_server* s, sssp_stats* stats);
+
+/* Stop (if needed) and release the server. NULL is accepted. Freeing its
+ * pinned ring waits for all work on the device, so stop every server that
+ * shares the device before destroying any of them. */
+sssp_status sssp_server_destroy(sssp_server* s);
 
 /* Static description of a status code. */
 const char* sssp_status_string(sssp_status s);

@@ -21,12 +21,15 @@ import numpy as np
 from . import _native as N
 from ._native import (SSSP_RULE_BF, SSSP_RULE_DELTA_STAR, SSSP_RULE_MIN, SSSP_RULE_RHO, sssp_abi_version,
                       sssp_default_params, sssp_graph_create, sssp_graph_destroy, sssp_graph_info,
-                      sssp_last_error, sssp_params, sssp_solve, sssp_stats, sssp_status_string, sssp_step_record,
-                      sssp_tuning)
+                      sssp_last_error, sssp_params, sssp_row_hash, sssp_server_destroy, sssp_server_poll,
+                      sssp_server_start, sssp_server_stop, sssp_server_submit, sssp_solve, sssp_stats,
+                      sssp_status_string, sssp_step_record, sssp_tuning)
 
-__all__ = ["Graph", "solve", "SSSPError", "to_numpy_u64", "RULES", "INF", "sssp_graph_create", "sssp_graph_destroy",
-           "sssp_graph_info", "sssp_solve", "sssp_status_string", "sssp_last_error", "sssp_abi_version",
-           "sssp_default_params", "sssp_params", "sssp_stats", "sssp_tuning", "sssp_step_record"]
+__all__ = ["Graph", "solve", "Server", "row_hash", "SSSPError", "to_numpy_u64", "RULES", "INF", "sssp_graph_create",
+           "sssp_graph_destroy", "sssp_graph_info", "sssp_solve", "sssp_status_string", "sssp_last_error",
+           "sssp_abi_version", "sssp_default_params", "sssp_params", "sssp_stats", "sssp_tuning",
+           "sssp_step_record", "sssp_row_hash", "sssp_server_start", "sssp_server_submit", "sssp_server_poll",
+           "sssp_server_stop", "sssp_server_destroy"]
 
 INF = 0xFFFFFFFFFFFFFFFF
 RULES = {"rho": SSSP_RULE_RHO, "delta": SSSP_RULE_DELTA_STAR, "delta_star": SSSP_RULE_DELTA_STAR,
@@ -163,6 +166,21 @@ def make_tuning(**kw) -> sssp_tuning:
     return t
 
 
+def _params(rule, rho, delta, seed, tuning, snapshot_keys=False):
+    p = sssp_params()
+    N.lib().sssp_default_params(ctypes.byref(p))
+    p.rule = RULES[rule]
+    p.rho = int(rho)
+    p.delta = int(delta)
+    p.seed = int(seed)
+    p.flags = N.SSSP_SOLVE_SNAPSHOT_KEYS if snapshot_keys else 0
+    tun = None
+    if tuning is not None:
+        tun = tuning if isinstance(tuning, sssp_tuning) else make_tuning(**tuning)
+        p.tuning = ctypes.pointer(tun)
+    return p, tun
+
+
 def solve(g: Graph, sources, rule: str = "rho", rho: int = 1 << 20, delta: int = 1 << 13, seed: int = 1,
           max_steps: int = 0, tuning: dict | sssp_tuning | None = None, out=None, stream=None,
           trace: int = 0, extract_counts: bool = False, snapshot_keys: bool = False):
@@ -179,18 +197,8 @@ def solve(g: Graph, sources, rule: str = "rho", rho: int = 1 << 20, delta: int =
         out = torch.empty((ns, g.n), dtype=torch.int64, device="cuda")
     elif out.dtype != torch.int64 or out.numel() != ns * g.n or not out.is_contiguous():
         raise ValueError("out must be a contiguous int64 CUDA tensor with n_src * n elements")
-    p = sssp_params()
-    N.lib().sssp_default_params(ctypes.byref(p))
-    p.rule = RULES[rule]
-    p.rho = int(rho)
-    p.delta = int(delta)
-    p.seed = int(seed)
+    p, tun = _params(rule, rho, delta, seed, tuning, snapshot_keys)
     p.max_steps = int(max_steps)
-    p.flags = N.SSSP_SOLVE_SNAPSHOT_KEYS if snapshot_keys else 0
-    tun = None
-    if tuning is not None:
-        tun = tuning if isinstance(tuning, sssp_tuning) else make_tuning(**tuning)
-        p.tuning = ctypes.pointer(tun)
     counts = None
     if extract_counts:
         counts = torch.zeros((ns, g.n), dtype=torch.int32, device="cuda")
@@ -217,6 +225,75 @@ def solve(g: Graph, sources, rule: str = "rho", rho: int = 1 << 20, delta: int =
                          "successes": int(r[4]), "flags": int(r[5]) & 0xFFFFFFFF, "samples": int(r[5]) >> 32})
         stats["trace"] = recs
     return out, stats
+
+
+def row_hash(row, stream=None) -> int:
+    """Order-independent checksum of one device distance row (sssp_row_hash)."""
+    rc, h = sssp_row_hash(ctypes.c_void_p(row.data_ptr()), row.numel(), _stream_ptr(stream))
+    if rc != N.SSSP_OK:
+        raise SSSPError(rc, "sssp_row_hash")
+    return h
+
+
+class Server:
+    """A persistent serving launch on one graph (sssp_server_*): requests are
+    posted while it runs and finish one by one into rows of `rows`, a
+    contiguous int64 CUDA tensor of shape (R, n) owned by the caller. The
+    library runs the launch on a hardware queue of its own; `stream` (default:
+    the current stream) only orders its start. While it runs, keep GPU work
+    off the default (NULL) stream, which HIP makes wait for the server's
+    blocking stream: use a side stream (torch.cuda.stream(torch.cuda.Stream()))."""
+
+    def __init__(self, g: Graph, rows, rule: str = "rho", rho: int = 1 << 20, delta: int = 1 << 13, seed: int = 1,
+                 tuning: dict | sssp_tuning | None = None, ring_capacity: int = 1024, hash_rows: bool = False,
+                 idle_ms: int = 0, stream=None):
+        if rows.dtype != _torch().int64 or rows.dim() != 2 or rows.shape[1] != g.n or not rows.is_contiguous():
+            raise ValueError("rows must be a contiguous int64 CUDA tensor of shape (R, n)")
+        self.g = g
+        self.rows = rows
+        self.stream = stream if stream is not None else _torch().cuda.current_stream()
+        p, self._tun = _params(rule, rho, delta, seed, tuning)
+        self._cap = int(ring_capacity)
+        rc, self._s = sssp_server_start(g._h, p, ctypes.c_void_p(rows.data_ptr()), rows.shape[0], self._cap,
+                                        N.SSSP_SERVE_HASH if hash_rows else 0, idle_ms,
+                                        ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != N.SSSP_OK:
+            raise SSSPError(rc, "sssp_server_start")
+        self._t = (ctypes.c_uint64 * self._cap)()
+        self._h = (ctypes.c_uint64 * self._cap)()
+        self.stats = None
+
+    def submit(self, source: int, row: int) -> int:
+        rc, t = sssp_server_submit(self._s, source, row)
+        if rc != N.SSSP_OK:
+            raise SSSPError(rc, "sssp_server_submit")
+        return t
+
+    def poll(self) -> list[tuple[int, int]]:
+        """(ticket, row checksum) of the requests finished since the last poll."""
+        rc, c = sssp_server_poll(self._s, self._t, self._h, self._cap)
+        if rc != N.SSSP_OK:
+            raise SSSPError(rc, "sssp_server_poll")
+        return [(self._t[i], self._h[i]) for i in range(c)]
+
+    def stop(self) -> dict:
+        st = sssp_stats()
+        rc = sssp_server_stop(self._s, st)
+        if rc != N.SSSP_OK:
+            raise SSSPError(rc, "sssp_server_stop")
+        self.stats = st.as_dict()
+        return self.stats
+
+    def close(self):
+        if getattr(self, "_s", None) is not None:
+            sssp_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def to_numpy_u64(t) -> np.ndarray:

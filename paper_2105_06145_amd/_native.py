@@ -44,6 +44,7 @@ SSSP_INPUT_DEVICE = 0x2
 SSSP_TRUST_INPUT = 0x4
 SSSP_KEEP_ORDER = 0x8
 SSSP_SOLVE_SNAPSHOT_KEYS = 0x1
+SSSP_SERVE_HASH = 0x1
 
 
 class sssp_tuning(ctypes.Structure):
@@ -121,6 +122,20 @@ def lib():
         L.sssp_last_error.restype = ctypes.c_char_p
         L.sssp_abi_version.argtypes = []
         L.sssp_abi_version.restype = ctypes.c_int
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        L.sssp_row_hash.argtypes = [vp, ctypes.c_int64, vp, u64p]
+        L.sssp_row_hash.restype = ctypes.c_int
+        L.sssp_server_start.argtypes = [vp, ctypes.POINTER(sssp_params), vp, ctypes.c_uint32, ctypes.c_uint32,
+                                        ctypes.c_uint32, ctypes.c_uint32, vp, ctypes.POINTER(vp)]
+        L.sssp_server_start.restype = ctypes.c_int
+        L.sssp_server_submit.argtypes = [vp, ctypes.c_int32, ctypes.c_uint32, u64p]
+        L.sssp_server_submit.restype = ctypes.c_int
+        L.sssp_server_poll.argtypes = [vp, u64p, u64p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
+        L.sssp_server_poll.restype = ctypes.c_int
+        L.sssp_server_stop.argtypes = [vp, ctypes.POINTER(sssp_stats)]
+        L.sssp_server_stop.restype = ctypes.c_int
+        L.sssp_server_destroy.argtypes = [vp]
+        L.sssp_server_destroy.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -156,6 +171,43 @@ def sssp_graph_info(handle):
 def sssp_solve(handle, sources_ptr, n_src, params: sssp_params, dist_ptr, stream_ptr, stats: sssp_stats | None):
     return lib().sssp_solve(handle, sources_ptr, int(n_src), ctypes.byref(params) if params is not None else None,
                             dist_ptr, stream_ptr, ctypes.byref(stats) if stats is not None else None)
+
+
+def sssp_row_hash(dist_ptr, n, stream_ptr):
+    """Returns (status, checksum)."""
+    h = ctypes.c_uint64()
+    rc = lib().sssp_row_hash(dist_ptr, int(n), stream_ptr, ctypes.byref(h))
+    return rc, h.value
+
+
+def sssp_server_start(handle, params: sssp_params, dist_ptr, rows, ring_capacity, flags, idle_ms, stream_ptr):
+    """Returns (status, server handle or None)."""
+    s = ctypes.c_void_p()
+    rc = lib().sssp_server_start(handle, ctypes.byref(params) if params is not None else None, dist_ptr, int(rows),
+                                 int(ring_capacity), int(flags), int(idle_ms), stream_ptr, ctypes.byref(s))
+    return rc, (s if rc == SSSP_OK else None)
+
+
+def sssp_server_submit(server, source, row):
+    """Returns (status, ticket)."""
+    t = ctypes.c_uint64()
+    rc = lib().sssp_server_submit(server, int(source), int(row), ctypes.byref(t))
+    return rc, t.value
+
+
+def sssp_server_poll(server, tickets, hashes, max_count):
+    """tickets / hashes: ctypes uint64 arrays (hashes may be None). Returns (status, count)."""
+    c = ctypes.c_uint32()
+    rc = lib().sssp_server_poll(server, tickets, hashes, int(max_count), ctypes.byref(c))
+    return rc, c.value
+
+
+def sssp_server_stop(server, stats: sssp_stats | None):
+    return lib().sssp_server_stop(server, ctypes.byref(stats) if stats is not None else None)
+
+
+def sssp_server_destroy(server) -> int:
+    return lib().sssp_server_destroy(server)
 
 
 def sssp_status_string(s: int) -> str:

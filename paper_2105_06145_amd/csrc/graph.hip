@@ -31,8 +31,9 @@ __global__ void widen_offsets_kernel(const int32_t* in, int64_t* out, ull count)
     out[i] = in[i];
 }
 
+// err occupies the low half of an 8-byte word that is read back whole.
 __global__ void reset_flags_kernel(unsigned* err, ull* where) {
-  *err = 0;
+  *reinterpret_cast<ull*>(err) = 0;
   *where = INF;
 }
 
@@ -99,14 +100,14 @@ sssp_status relabel_by_degree(sssp_graph* g, hipStream_t st) {
   const ull n = (ull)g->n, m = (ull)g->m;
   DevBuf keys, keys2, ids, newdeg, newoff, newedges, tmp;
   auto cleanup = [&]() {
-    for (DevBuf* b : {&keys, &keys2, &ids, &newdeg, &newoff, &newedges, &tmp}) b->release();
+    for (DevBuf* b : {&keys, &keys2, &ids, &newdeg, &newoff, &newedges, &tmp}) b->release(st);
   };
   hipError_t e;
   do {
-    if ((e = keys.alloc(n * 4)) != hipSuccess || (e = keys2.alloc(n * 4)) != hipSuccess ||
-        (e = ids.alloc(n * 4)) != hipSuccess || (e = g->perm.alloc(n * 4)) != hipSuccess ||
-        (e = g->inv.alloc(n * 4)) != hipSuccess || (e = newdeg.alloc((n + 1) * 8)) != hipSuccess ||
-        (e = newoff.alloc((n + 1) * 8)) != hipSuccess || (e = newedges.alloc(m * 8)) != hipSuccess)
+    if ((e = keys.alloc(n * 4, st)) != hipSuccess || (e = keys2.alloc(n * 4, st)) != hipSuccess ||
+        (e = ids.alloc(n * 4, st)) != hipSuccess || (e = g->perm.alloc(n * 4, st)) != hipSuccess ||
+        (e = g->inv.alloc(n * 4, st)) != hipSuccess || (e = newdeg.alloc((n + 1) * 8, st)) != hipSuccess ||
+        (e = newoff.alloc((n + 1) * 8, st)) != hipSuccess || (e = newedges.alloc(m * 8, st)) != hipSuccess)
       break;
     degree_keys_kernel<<<1024, 256, 0, st>>>((const int64_t*)g->off.p, n, (uint32_t*)keys.p, (int32_t*)ids.p);
     if ((e = hipGetLastError()) != hipSuccess) break;
@@ -114,7 +115,7 @@ sssp_status relabel_by_degree(sssp_graph* g, hipStream_t st) {
     if ((e = rocprim::radix_sort_pairs(nullptr, bytes, (uint32_t*)keys.p, (uint32_t*)keys2.p, (int32_t*)ids.p,
                                        (int32_t*)g->perm.p, (size_t)n, 0, 32, st)) != hipSuccess)
       break;
-    if ((e = tmp.alloc(bytes)) != hipSuccess) break;
+    if ((e = tmp.alloc(bytes, st)) != hipSuccess) break;
     if ((e = rocprim::radix_sort_pairs(tmp.p, bytes, (uint32_t*)keys.p, (uint32_t*)keys2.p, (int32_t*)ids.p,
                                        (int32_t*)g->perm.p, (size_t)n, 0, 32, st)) != hipSuccess)
       break;
@@ -125,7 +126,7 @@ sssp_status relabel_by_degree(sssp_graph* g, hipStream_t st) {
     if ((e = rocprim::exclusive_scan(nullptr, sbytes, (int64_t*)newdeg.p, (int64_t*)newoff.p, (int64_t)0,
                                      (size_t)(n + 1), rocprim::plus<int64_t>(), st)) != hipSuccess)
       break;
-    if (sbytes > tmp.bytes && (e = tmp.alloc(sbytes)) != hipSuccess) break;
+    if (sbytes > tmp.bytes && (e = tmp.alloc(sbytes, st)) != hipSuccess) break;
     if ((e = rocprim::exclusive_scan(tmp.p, sbytes, (int64_t*)newdeg.p, (int64_t*)newoff.p, (int64_t)0,
                                      (size_t)(n + 1), rocprim::plus<int64_t>(), st)) != hipSuccess)
       break;
@@ -142,8 +143,8 @@ sssp_status relabel_by_degree(sssp_graph* g, hipStream_t st) {
   } while (false);
   cleanup();
   if (e != hipSuccess) {
-    g->perm.release();
-    g->inv.release();
+    g->perm.release(st);
+    g->inv.release(st);
     return fail(from_hip(e), std::string("relabel: ") + hipGetErrorString(e));
   }
   return SSSP_OK;
@@ -178,6 +179,7 @@ const char* sssp_last_error(void) { return last_error().c_str(); }
 
 sssp_status sssp_graph_destroy(sssp_graph* g) {
   if (!g) return SSSP_OK;
+  if (g->serving) return fail(SSSP_ERR_INVALID_ARGUMENT, "a server is running on this graph; stop it first");
   (void)hipSetDevice(g->device);
   g->release_all();
   delete g;
@@ -250,12 +252,12 @@ sssp_status sssp_graph_create(int64_t n, int64_t m, sssp_offset_width ow, const 
   std::string msg;
   hipError_t e = hipSuccess;
   do {
-    if ((e = g->off.alloc((size_t)(n + 1) * 8)) != hipSuccess) break;
-    if ((e = g->edges.alloc((size_t)m * 8)) != hipSuccess) break;
+    if ((e = g->off.alloc((size_t)(n + 1) * 8, st)) != hipSuccess) break;
+    if ((e = g->edges.alloc((size_t)m * 8, st)) != hipSuccess) break;
     if (ow == SSSP_OFFSETS_I64) {
       if ((e = hipMemcpyAsync(g->off.p, offsets, (size_t)(n + 1) * 8, kind, st)) != hipSuccess) break;
     } else {
-      if ((e = o32.alloc((size_t)(n + 1) * 4)) != hipSuccess) break;
+      if ((e = o32.alloc((size_t)(n + 1) * 4, st)) != hipSuccess) break;
       if ((e = hipMemcpyAsync(o32.p, offsets, (size_t)(n + 1) * 4, kind, st)) != hipSuccess) break;
       widen_offsets_kernel<<<1024, 256, 0, st>>>((const int32_t*)o32.p, (int64_t*)g->off.p, (ull)(n + 1));
       if ((e = hipGetLastError()) != hipSuccess) break;
@@ -263,15 +265,15 @@ sssp_status sssp_graph_create(int64_t n, int64_t m, sssp_offset_width ow, const 
     const int32_t* tsrc = targets;
     const uint32_t* wsrc = weights;
     if (m > 0 && host) {
-      if ((e = t32.alloc((size_t)m * 4)) != hipSuccess) break;
-      if ((e = w32.alloc((size_t)m * 4)) != hipSuccess) break;
+      if ((e = t32.alloc((size_t)m * 4, st)) != hipSuccess) break;
+      if ((e = w32.alloc((size_t)m * 4, st)) != hipSuccess) break;
       if ((e = hipMemcpyAsync(t32.p, targets, (size_t)m * 4, hipMemcpyHostToDevice, st)) != hipSuccess) break;
       if ((e = hipMemcpyAsync(w32.p, weights, (size_t)m * 4, hipMemcpyHostToDevice, st)) != hipSuccess) break;
       tsrc = (const int32_t*)t32.p;
       wsrc = (const uint32_t*)w32.p;
     }
     if (device && !trust) {
-      if ((e = flag.alloc(16)) != hipSuccess) break;
+      if ((e = flag.alloc(16, st)) != hipSuccess) break;
       reset_flags_kernel<<<1, 1, 0, st>>>((unsigned*)flag.p, (ull*)flag.p + 1);
       validate_kernel<<<1024, 256, 0, st>>>((const int64_t*)g->off.p, tsrc, (ull)n, (ull)m, (unsigned*)flag.p,
                                             (ull*)flag.p + 1);
@@ -280,7 +282,7 @@ sssp_status sssp_graph_create(int64_t n, int64_t m, sssp_offset_width ow, const 
           (e = hipMemcpyAsync(back, flag.p, 16, hipMemcpyDeviceToHost, st)) == hipSuccess)
         e = hipStreamSynchronize(st);
       if (e != hipSuccess) break;
-      if (back[0]) {
+      if ((unsigned)back[0]) {
         rs = SSSP_ERR_INVALID_GRAPH;
         msg = "device CSR validation failed (code " + std::to_string((unsigned)back[0]) + ", index " +
               std::to_string(back[1] == INF ? -1LL : (long long)back[1]) + ")";
@@ -293,10 +295,10 @@ sssp_status sssp_graph_create(int64_t n, int64_t m, sssp_offset_width ow, const 
     }
     e = hipStreamSynchronize(st);
   } while (false);
-  t32.release();
-  w32.release();
-  o32.release();
-  flag.release();
+  t32.release(st);
+  w32.release(st);
+  o32.release(st);
+  flag.release(st);
   if (e == hipSuccess && rs == SSSP_OK && !(flags & SSSP_KEEP_ORDER)) rs = relabel_by_degree(g, st);
   if (e != hipSuccess) {
     sssp_graph_destroy(g);

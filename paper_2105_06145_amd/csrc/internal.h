@@ -35,17 +35,19 @@ inline sssp_status from_hip(hipError_t e) {
                                std::string(#expr) + ": " + hipGetErrorString(e_));           \
   } while (0)
 
-// Owned device allocation.
+// Owned device allocation, stream-ordered: allocating and freeing wait only
+// for work on the given stream (hipFree would wait for the whole device, and
+// with it for a persistent serving launch that runs until it is stopped).
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
-  hipError_t alloc(size_t b) {
-    release();
+  hipError_t alloc(size_t b, hipStream_t st) {
+    release(st);
     bytes = b;
-    return hipMalloc(&p, b ? b : 8);
+    return hipMallocAsync(&p, b ? b : 8, st);
   }
-  void release() {
-    if (p) (void)hipFree(p);
+  void release(hipStream_t st) {
+    if (p) (void)hipFreeAsync(p, st);
     p = nullptr;
     bytes = 0;
   }
@@ -66,32 +68,33 @@ struct sssp_graph {
   sssp_impl::DevBuf edges;  // uint64[m]: (weight << 32) | internal target
   sssp_impl::DevBuf perm, inv;
   bool relabelled = false;
+  bool serving = false;  // a persistent server owns the workspace
   // Workspace.
   bool ws_ready = false;
   uint32_t ws_hub_degree = 0, ws_chunk = 0, ws_probe_cap = 0, ws_G = 0, ws_teams = 0;
   uint64_t ws_src_cap = 0;  // sources the `srcs` buffer holds
   sssp_impl::DevBuf dist_int, bitmap, hubmask, F, FD, H, L, samples, parts, ctl, args, srcs;
-  void* hargs = nullptr;  // pinned staging copy of the kernel arguments
+  void* hargs = nullptr;  // host staging copy of the kernel arguments (operator new)
 
   uint64_t graph_bytes() const { return off.bytes + edges.bytes + perm.bytes + inv.bytes; }
   uint64_t workspace_bytes() const {
     return dist_int.bytes + bitmap.bytes + hubmask.bytes + F.bytes + FD.bytes + H.bytes + L.bytes + samples.bytes +
            parts.bytes + ctl.bytes + args.bytes + srcs.bytes;
   }
-  void release_ws() {
+  void release_ws(hipStream_t st) {
     for (sssp_impl::DevBuf* b : {&dist_int, &bitmap, &hubmask, &F, &FD, &H, &L, &samples, &parts, &ctl, &args, &srcs})
-      b->release();
-    if (hargs) (void)hipHostFree(hargs);
-    hargs = nullptr;
+      b->release(st);
     ws_ready = false;
     ws_src_cap = 0;
   }
   void release_all() {
-    release_ws();
-    off.release();
-    edges.release();
-    perm.release();
-    inv.release();
+    release_ws(nullptr);
+    off.release(nullptr);
+    edges.release(nullptr);
+    perm.release(nullptr);
+    inv.release(nullptr);
+    ::operator delete(hargs);
+    hargs = nullptr;
   }
 };
 

@@ -59,7 +59,9 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <new>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 
@@ -105,6 +107,10 @@ struct TeamCtl {
   ull st_qdense, st_qlist, st_appends;
   ull relax_busy_max, relax_busy_sum;
   ull phase_ticks[4];  // init, threshold, extract, relax (the team's first workgroup)
+  // Serving: the current request and the one still to be published.
+  ull src, out_row;
+  ull hash_acc;  // row checksum, summed over the team's workgroups
+  ull pending;   // ticket + 1 of a finished request not yet published (0: none)
   alignas(128) StepSlot slot[3];
 };
 
@@ -174,7 +180,21 @@ struct KArgs {
   uint32_t probe_cap;
   uint32_t filter;
   uint32_t snapshot;  // relax with the keys at extraction
+  // Serving mode: requests come from a ring in host memory instead of srcs.
+  uint32_t serve;
+  uint32_t hash;               // add each finished row's checksum to its ring entry
+  const int32_t* req;          // host: ring_cap x (source, row); ticket t uses entry t % ring_cap
+  const uint64_t* posted;      // host: requests posted so far
+  const uint32_t* closed;      // host: nonzero once no more requests will come
+  uint64_t* ack;               // host: ring_cap entries, ticket + 1 once taken (entry free again)
+  uint64_t* done;              // host: per row, ticket + 1 once its request finished
+  uint64_t* hashes;            // host: per row, the finished row's checksum
+  uint64_t ring_cap;
+  uint64_t nrows;              // rows of dist_out
+  uint64_t idle_ticks;         // longest wait for a request
 };
+
+constexpr ull SERVE_EXIT = ~0ull;
 
 struct Shared {
   ull beg[WG];
@@ -913,6 +933,76 @@ __device__ __noinline__ void step_bookkeeping(const KArgs& a, StepSlot* S, ull t
 }
 
 // ---------------------------------------------------------------------------
+// Serving.
+
+// Order-independent checksum of a distance row: the sum over v of a 64-bit
+// mix of (v, delta[v]) (the SplitMix64 finaliser), modulo 2^64.
+__device__ __forceinline__ ull row_mix(ull v, ull d) {
+  ull z = d ^ (v * 0x9e3779b97f4a7c15ull);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+template <class T>
+__device__ __forceinline__ T ld_system(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Serial part of a serving team's claim barrier (thread 0 of one workgroup):
+// publish the request the team finished (its row and checksum first, then
+// its row's completion word), then take the next ticket, wait until the host
+// has posted that request, copy it out of the ring and acknowledge it (which
+// frees its ring entry). Leaves the ticket, or SERVE_EXIT once the host has
+// closed the ring (and every posted request is taken), in tc->query. The wait
+// is bounded by idle_ticks and the abort flag.
+__device__ __noinline__ void serve_claim(const KArgs& a, TeamCtl* tc, GridCtl* gc) {
+  if (tc->pending) {
+    const ull t = tc->pending - 1, row = tc->out_row;
+    const ull h = ld_agent(&tc->hash_acc);
+    tc->hash_acc = 0;
+    tc->pending = 0;
+    __hip_atomic_store(&a.hashes[row], h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&a.done[row], t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  for (;;) {
+    const ull t = atom_add(&gc->next_query.v, 1ull);
+    const long long t0 = wall_clock64();
+    bool have = false;
+    for (;;) {
+      if (ld_system(a.posted) > t) {
+        have = true;
+        break;
+      }
+      if (ld_system(a.closed)) {
+        have = ld_system(a.posted) > t;  // posted is written before closed
+        break;
+      }
+      if (__hip_atomic_load(&gc->abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+      if ((ull)(wall_clock64() - t0) > a.idle_ticks) break;
+      __builtin_amdgcn_s_sleep(64);
+    }
+    if (!have) {
+      tc->query = SERVE_EXIT;
+      return;
+    }
+    const ull e = t % a.ring_cap;
+    const int32_t src = ld_system(&a.req[2 * e]);
+    const uint32_t row = (uint32_t)ld_system(&a.req[2 * e + 1]);
+    __hip_atomic_store(&a.ack[e], t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (src >= 0 && src < a.n && row < a.nrows) {
+      tc->src = (ull)src;
+      tc->out_row = row;
+      tc->pending = t + 1;
+      tc->query = t;
+      return;
+    }
+    // A malformed entry (the host checks requests before posting them) is
+    // acknowledged and dropped.
+  }
+}
+
+// ---------------------------------------------------------------------------
 // The persistent kernel.
 
 __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict__ A) {
@@ -987,14 +1077,27 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
   ph0 += lap();
 
   for (;;) {
-    // Take the next source.
+    // Take the next source (serving: publish the finished request, then wait
+    // for the next one).
     auto claim = [&]() {
-      if (tid == 0) tm.ctl->query = atom_add(&gc->next_query.v, 1ull);
+      if (tid != 0) return;
+      if (a.serve) {
+        serve_claim(a, tm.ctl, gc);
+      } else {
+        tm.ctl->query = atom_add(&gc->next_query.v, 1ull);
+      }
     };
+    if (a.serve) {
+      // The finished row must be visible outside the device (system scope)
+      // before the claim publishes it.
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    }
     if (!team_sync(a, sh, tm, claim)) return;
     const ull qi = ld_agent(&tm.ctl->query);
-    if (qi >= (ull)a.n_src) break;
-    ull* out = a.dist_out + qi * n;
+    if (a.serve ? qi == SERVE_EXIT : qi >= (ull)a.n_src) break;
+    ull* out = a.dist_out + (a.serve ? ld_agent(&tm.ctl->out_row) : qi) * n;
     if (!a.dist_int) dist = out;
 
     // S0: delta = inf, Q empty; then delta[s] = 0 and Update(s).
@@ -1004,7 +1107,7 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
       auto seed_source = [&]() {
         if (tid < 48) reinterpret_cast<ull*>(&tm.ctl->slot[0])[tid] = 0ull;
         if (tid == 0) {
-          const int32_t src = a.srcs[qi];
+          const int32_t src = a.serve ? (int32_t)tm.ctl->src : a.srcs[qi];
           const int32_t s = a.inv ? a.inv[src] : src;
           dist[s] = 0;
           tm.bitmap[s >> 6] = 1ull << (s & 63);
@@ -1086,9 +1189,21 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
       list_valid = emit && ld_agent(&S->list_next) <= a.lcap;
       if (dense) ++dense_steps;
     }
-    // Distances back in the caller's vertex ids.
-    if (a.dist_int)
-      for (ull v = tm.rank * WG + tid; v < n; v += tm.T * WG) out[v] = ld_agent(&dist[a.inv[v]]);
+    // Distances back in the caller's vertex ids, and the row checksum.
+    ull h = 0;
+    if (a.dist_int) {
+      for (ull v = tm.rank * WG + tid; v < n; v += tm.T * WG) {
+        const ull d = ld_agent(&dist[a.inv[v]]);
+        out[v] = d;
+        if (a.hash) h += row_mix(v, d);
+      }
+    } else if (a.hash) {
+      for (ull v = tm.rank * WG + tid; v < n; v += tm.T * WG) h += row_mix(v, ld_agent(&out[v]));
+    }
+    if (a.hash) {
+      h = wave_sum(h);
+      if (lane_id() == 0) atom_add(&tm.ctl->hash_acc, h);
+    }
   }
   if (tm.rank == 0 && tid == 0) {
     tm.ctl->phase_ticks[0] += ph0;
@@ -1181,20 +1296,23 @@ sssp_status ensure_workspace(sssp_graph* g, const sssp_tuning& tu, const Geometr
   if (g->ws_ready && g->ws_hub_degree == tu.hub_degree && g->ws_chunk == tu.chunk_edges &&
       g->ws_probe_cap >= tu.probe_cap && g->ws_G == geo.G && g->ws_teams == geo.nteams)
     return SSSP_OK;
-  g->release_ws();
+  g->release_ws(st);
   const uint64_t n = (uint64_t)g->n, nt = geo.nteams;
-  if (g->relabelled) SSSP_HIP_TRY(g->dist_int.alloc(nt * n * 8));
-  SSSP_HIP_TRY(g->bitmap.alloc(nt * geo.nwords * 8));
-  SSSP_HIP_TRY(g->hubmask.alloc(geo.nwords * 8));
-  SSSP_HIP_TRY(g->F.alloc((uint64_t)geo.G * geo.segcap * 4));
-  SSSP_HIP_TRY(g->FD.alloc((uint64_t)geo.G * geo.segcap * 8));
-  SSSP_HIP_TRY(g->H.alloc(nt * geo.hcap * 16));
-  SSSP_HIP_TRY(g->L.alloc(nt * 2 * geo.lcap * 4));
-  SSSP_HIP_TRY(g->samples.alloc(nt * (uint64_t)tu.probe_cap * 8));
-  SSSP_HIP_TRY(g->parts.alloc((uint64_t)geo.G * sizeof(Part)));
-  SSSP_HIP_TRY(g->ctl.alloc(control_words(geo.nteams) * 8));
-  SSSP_HIP_TRY(g->args.alloc(sizeof(KArgs)));
-  SSSP_HIP_TRY(hipHostMalloc(&g->hargs, sizeof(KArgs), hipHostMallocDefault));
+  if (g->relabelled) SSSP_HIP_TRY(g->dist_int.alloc(nt * n * 8, st));
+  SSSP_HIP_TRY(g->bitmap.alloc(nt * geo.nwords * 8, st));
+  SSSP_HIP_TRY(g->hubmask.alloc(geo.nwords * 8, st));
+  SSSP_HIP_TRY(g->F.alloc((uint64_t)geo.G * geo.segcap * 4, st));
+  SSSP_HIP_TRY(g->FD.alloc((uint64_t)geo.G * geo.segcap * 8, st));
+  SSSP_HIP_TRY(g->H.alloc(nt * geo.hcap * 16, st));
+  SSSP_HIP_TRY(g->L.alloc(nt * 2 * geo.lcap * 4, st));
+  SSSP_HIP_TRY(g->samples.alloc(nt * (uint64_t)tu.probe_cap * 8, st));
+  SSSP_HIP_TRY(g->parts.alloc((uint64_t)geo.G * sizeof(Part), st));
+  SSSP_HIP_TRY(g->ctl.alloc(control_words(geo.nteams) * 8, st));
+  SSSP_HIP_TRY(g->args.alloc(sizeof(KArgs), st));
+  if (!g->hargs) {
+    g->hargs = ::operator new(sizeof(KArgs), std::nothrow);
+    if (!g->hargs) return fail(SSSP_ERR_OUT_OF_MEMORY, "kernel argument staging");
+  }
   hubmask_kernel<<<1024, 256, 0, st>>>((const int64_t*)g->off.p, n, geo.nwords, tu.hub_degree, (ull*)g->hubmask.p);
   SSSP_HIP_TRY(hipGetLastError());
   g->ws_ready = true;
@@ -1217,26 +1335,18 @@ uint32_t auto_teams(int32_t n_src, uint32_t G) {
   return t;
 }
 
-}  // namespace
 
-extern "C" {
-
-void sssp_default_params(sssp_params* p) {
-  if (!p) return;
-  std::memset(p, 0, sizeof(*p));
-  p->rule = SSSP_RULE_RHO;
-  p->rho = 1ull << 20;
-  p->delta = 1ull << 13;
-  p->seed = 1;
-}
-
-sssp_status sssp_solve(const sssp_graph* gc, const int32_t* sources, int32_t n_src, const sssp_params* params,
-                       uint64_t* dist, void* stream, sssp_stats* stats) {
-  last_error().clear();
-  if (!gc) return fail(SSSP_ERR_INVALID_ARGUMENT, "graph is NULL");
-  if (n_src < 0) return fail(SSSP_ERR_INVALID_ARGUMENT, "n_src < 0");
-  if (n_src > 0 && (!sources || !dist)) return fail(SSSP_ERR_INVALID_ARGUMENT, "sources or dist is NULL");
+// Shared set-up of a launch: parameter checks, grid, teams, workspace and the
+// kernel arguments (everything but the source list and the serving ring).
+struct Launch {
   sssp_params p;
+  sssp_tuning tu;
+  uint32_t G = 0, nteams = 0;
+  Geometry geo;
+  KArgs a;
+};
+
+sssp_status check_params(const sssp_params* params, sssp_params& p, sssp_tuning& tu) {
   if (params) {
     p = *params;
   } else {
@@ -1247,36 +1357,31 @@ sssp_status sssp_solve(const sssp_graph* gc, const int32_t* sources, int32_t n_s
   if (p.rule == SSSP_RULE_RHO && p.rho == 0) return fail(SSSP_ERR_INVALID_ARGUMENT, "rho must be >= 1");
   if (p.rule == SSSP_RULE_DELTA_STAR && p.delta == 0) return fail(SSSP_ERR_INVALID_ARGUMENT, "delta must be >= 1");
   if (p.trace && p.trace_capacity == 0) return fail(SSSP_ERR_INVALID_ARGUMENT, "trace needs trace_capacity > 0");
-  for (int32_t i = 0; i < n_src; ++i)
-    if (sources[i] < 0 || sources[i] >= gc->n)
-      return fail(SSSP_ERR_INVALID_ARGUMENT, "source " + std::to_string(sources[i]) + " out of range");
-  sssp_tuning tu = resolve_tuning(p.tuning);
+  tu = resolve_tuning(p.tuning);
   if (tu.chunk_edges < 64) return fail(SSSP_ERR_INVALID_ARGUMENT, "chunk_edges must be >= 64");
   if (tu.hub_degree > (1u << 22)) return fail(SSSP_ERR_INVALID_ARGUMENT, "hub_degree must be <= 2^22");
   if (tu.sample_cap > tu.probe_cap) return fail(SSSP_ERR_INVALID_ARGUMENT, "sample_cap must be <= probe_cap");
-  if (stats) std::memset(stats, 0, sizeof(*stats));
-  if (n_src == 0) return SSSP_OK;
+  return SSSP_OK;
+}
 
-  sssp_graph* g = const_cast<sssp_graph*>(gc);
+sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uint64_t* dist, hipStream_t st) {
   SSSP_HIP_TRY(hipSetDevice(g->device));
-  hipStream_t st = (hipStream_t)stream;
   int occ = 0;
   SSSP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, stepping_kernel, WG, 0));
   if (occ < 1) return fail(SSSP_ERR_NO_DEVICE, "stepping kernel cannot be resident");
-  const uint32_t bpc = std::min<uint32_t>(tu.blocks_per_cu, (uint32_t)occ);
-  const uint32_t G = bpc * (uint32_t)g->cus;
-  const uint32_t nteams = tu.teams ? tu.teams : auto_teams(n_src, G);
-  if (nteams > G || G % nteams != 0)
-    return fail(SSSP_ERR_INVALID_ARGUMENT, "teams must divide the grid of " + std::to_string(G) + " workgroups");
-  const Geometry geo = make_geometry(g, tu, G, nteams);
-  sssp_status ws = ensure_workspace(g, tu, geo, st);
+  const uint32_t bpc = std::min<uint32_t>(L.tu.blocks_per_cu, (uint32_t)occ);
+  L.G = bpc * (uint32_t)g->cus;
+  L.nteams = L.tu.teams ? L.tu.teams : default_teams;
+  if (L.nteams > L.G || L.G % L.nteams != 0)
+    return fail(SSSP_ERR_INVALID_ARGUMENT, "teams must divide the grid of " + std::to_string(L.G) + " workgroups");
+  L.geo = make_geometry(g, L.tu, L.G, L.nteams);
+  sssp_status ws = ensure_workspace(g, L.tu, L.geo, st);
   if (ws != SSSP_OK) return ws;
-  if ((uint64_t)n_src > g->ws_src_cap) {
-    SSSP_HIP_TRY(g->srcs.alloc((uint64_t)n_src * 4));
-    g->ws_src_cap = (uint64_t)n_src;
-  }
 
-  KArgs a;
+  const sssp_params& p = L.p;
+  const sssp_tuning& tu = L.tu;
+  const Geometry& geo = L.geo;
+  KArgs& a = L.a;
   std::memset(&a, 0, sizeof(a));
   a.n = g->n;
   a.nwords = geo.nwords;
@@ -1285,7 +1390,6 @@ sssp_status sssp_solve(const sssp_graph* gc, const int32_t* sources, int32_t n_s
   a.hubmask = (const ull*)g->hubmask.p;
   a.perm = g->relabelled ? (const int32_t*)g->perm.p : nullptr;
   a.inv = g->relabelled ? (const int32_t*)g->inv.p : nullptr;
-  a.srcs = (const int32_t*)g->srcs.p;
   a.dist_out = (ull*)dist;
   a.dist_int = g->relabelled ? (ull*)g->dist_int.p : nullptr;
   a.bitmap = (ull*)g->bitmap.p;
@@ -1310,74 +1414,392 @@ sssp_status sssp_solve(const sssp_graph* gc, const int32_t* sources, int32_t n_s
   a.segcap = geo.segcap;
   a.hcap = geo.hcap;
   a.lcap = geo.lcap;
-  a.n_src = n_src;
   a.rule = p.rule;
-  a.G = G;
-  a.nteams = nteams;
+  a.G = L.G;
+  a.nteams = L.nteams;
   a.chunk_edges = tu.chunk_edges;
   a.sample_cap = tu.sample_cap;
   a.probe_cap = tu.probe_cap;
   a.filter = tu.no_filter ? 0u : 1u;
   a.snapshot = (p.flags & SSSP_SOLVE_SNAPSHOT_KEYS) ? 1u : 0u;
+  return SSSP_OK;
+}
+
+// Copy the kernel arguments to the device and clear the control blocks.
+hipError_t stage_launch(sssp_graph* g, const Launch& L, hipStream_t st) {
+  std::memcpy(g->hargs, &L.a, sizeof(KArgs));
+  hipError_t e = hipMemcpyAsync(g->args.p, g->hargs, sizeof(KArgs), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  reset_control_kernel<<<64, 256, 0, st>>>((ull*)g->ctl.p, control_words(L.nteams));
+  return hipGetLastError();
+}
+
+// Read the control blocks back (after the kernel finished) into stats.
+// Returns the abort and step-limit indications.
+sssp_status collect_stats(sssp_graph* g, const Launch& L, hipStream_t st, sssp_stats* stats, bool& aborted,
+                          bool& step_limit) {
+  GridCtl hg;
+  std::string hteams((size_t)L.nteams * sizeof(TeamCtl), '\0');
+  SSSP_HIP_TRY(hipMemcpyAsync(&hg, g->ctl.p, sizeof(GridCtl), hipMemcpyDeviceToHost, st));
+  SSSP_HIP_TRY(
+      hipMemcpyAsync(&hteams[0], (char*)g->ctl.p + sizeof(GridCtl), hteams.size(), hipMemcpyDeviceToHost, st));
+  SSSP_HIP_TRY(hipStreamSynchronize(st));
+  aborted = hg.abort_flag != 0;
+  step_limit = false;
+  for (uint32_t t = 0; t < L.nteams; ++t) {
+    TeamCtl tc;
+    std::memcpy(&tc, &hteams[(size_t)t * sizeof(TeamCtl)], sizeof(TeamCtl));
+    step_limit |= (tc.status & ST_STEP_LIMIT) != 0;
+    if (!stats) continue;
+    stats->steps += tc.st_steps;
+    stats->extracted += tc.st_extracted;
+    stats->edges_relaxed += tc.st_edges;
+    stats->writemin_success += tc.st_success;
+    stats->dense_steps += tc.st_dense;
+    stats->sampled_steps += tc.st_sampled;
+    stats->queue_dense += tc.st_qdense;
+    stats->queue_list += tc.st_qlist;
+    stats->list_appends += tc.st_appends;
+    if (t == 0) {
+      for (int k = 0; k < 4; ++k) stats->phase_ms[k] = (double)tc.phase_ticks[k] / (double)g->tick_khz;
+      stats->relax_wg_ms[0] = (double)tc.relax_busy_max / (double)g->tick_khz;
+      stats->relax_wg_ms[1] = (double)tc.relax_busy_sum / (double)L.geo.T / (double)g->tick_khz;
+    }
+  }
+  if (stats) stats->teams = L.nteams;
+  return SSSP_OK;
+}
+
+// Checksum of one distance row (the same mix as the serving kernel's).
+__global__ void row_hash_kernel(const ull* dist, ull n, ull* out) {
+  ull h = 0;
+  for (ull v = (ull)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (ull)gridDim.x * blockDim.x)
+    h += row_mix(v, dist[v]);
+  h = wave_sum(h);
+  if (lane_id() == 0) atom_add(out, h);
+}
+
+}  // namespace
+
+// A persistent serving launch on one graph (include/sssp.h).
+struct sssp_server {
+  sssp_graph* g = nullptr;
+  hipStream_t caller = nullptr;  // orders the start after the caller's queued work
+  hipStream_t st = nullptr;      // the server's own stream (a hardware queue of its own)
+  Launch L;
+  uint64_t n = 0, rows = 0, cap = 0;
+  // Ring and completion words in pinned, coherent host memory, shared with
+  // the kernel: req[cap] pairs, then posted, closed, ack[cap], done[rows],
+  // hashes[rows].
+  int32_t* req = nullptr;
+  uint64_t* words = nullptr;
+  uint64_t* posted = nullptr;
+  uint32_t* closed = nullptr;
+  uint64_t* ack = nullptr;
+  uint64_t* done = nullptr;
+  uint64_t* hashes = nullptr;
+  uint64_t next_ticket = 0;
+  std::vector<uint64_t> row_ticket;  // per row: ticket + 1 of its unfinished request, or 0
+  std::vector<uint32_t> busy_rows;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool stopped = false;
+  sssp_status stop_status = SSSP_OK;
+  sssp_stats final_stats{};
+};
+
+extern "C" {
+
+void sssp_default_params(sssp_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->rule = SSSP_RULE_RHO;
+  p->rho = 1ull << 20;
+  p->delta = 1ull << 13;
+  p->seed = 1;
+}
+
+sssp_status sssp_solve(const sssp_graph* gc, const int32_t* sources, int32_t n_src, const sssp_params* params,
+                       uint64_t* dist, void* stream, sssp_stats* stats) {
+  last_error().clear();
+  if (!gc) return fail(SSSP_ERR_INVALID_ARGUMENT, "graph is NULL");
+  if (gc->serving) return fail(SSSP_ERR_INVALID_ARGUMENT, "a server is running on this graph");
+  if (n_src < 0) return fail(SSSP_ERR_INVALID_ARGUMENT, "n_src < 0");
+  if (n_src > 0 && (!sources || !dist)) return fail(SSSP_ERR_INVALID_ARGUMENT, "sources or dist is NULL");
+  Launch L;
+  sssp_status ps = check_params(params, L.p, L.tu);
+  if (ps != SSSP_OK) return ps;
+  for (int32_t i = 0; i < n_src; ++i)
+    if (sources[i] < 0 || sources[i] >= gc->n)
+      return fail(SSSP_ERR_INVALID_ARGUMENT, "source " + std::to_string(sources[i]) + " out of range");
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (n_src == 0) return SSSP_OK;
+
+  sssp_graph* g = const_cast<sssp_graph*>(gc);
+  hipStream_t st = (hipStream_t)stream;
+  {
+    // The default team count needs the grid size, which prepare_launch
+    // computes; resolve it there through a provisional value.
+    int occ = 0;
+    SSSP_HIP_TRY(hipSetDevice(g->device));
+    SSSP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, stepping_kernel, WG, 0));
+    const uint32_t G = std::max(1u, std::min<uint32_t>(L.tu.blocks_per_cu, (uint32_t)std::max(occ, 1))) *
+                       (uint32_t)g->cus;
+    sssp_status s = prepare_launch(g, L, auto_teams(n_src, G), dist, st);
+    if (s != SSSP_OK) return s;
+  }
+  if ((uint64_t)n_src > g->ws_src_cap) {
+    SSSP_HIP_TRY(g->srcs.alloc((uint64_t)n_src * 4, st));
+    g->ws_src_cap = (uint64_t)n_src;
+  }
+  L.a.srcs = (const int32_t*)g->srcs.p;
+  L.a.n_src = n_src;
 
   hipEvent_t ev0, ev1;
   SSSP_HIP_TRY(hipEventCreate(&ev0));
   SSSP_HIP_TRY(hipEventCreate(&ev1));
-  std::memcpy(g->hargs, &a, sizeof(KArgs));
-  const uint64_t cw = control_words(nteams);
   hipError_t e = hipMemcpyAsync(g->srcs.p, sources, (size_t)n_src * 4, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(g->args.p, g->hargs, sizeof(KArgs), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) {
-    reset_control_kernel<<<64, 256, 0, st>>>((ull*)g->ctl.p, cw);
-    e = hipGetLastError();
-  }
+  if (e == hipSuccess) e = stage_launch(g, L, st);
   if (e == hipSuccess) e = hipEventRecord(ev0, st);
   if (e == hipSuccess) {
     const KArgs* dargs = (const KArgs*)g->args.p;
     void* kargs[] = {(void*)&dargs};
-    e = hipLaunchCooperativeKernel((const void*)stepping_kernel, dim3(G), dim3(WG), kargs, 0, st);
+    e = hipLaunchCooperativeKernel((const void*)stepping_kernel, dim3(L.G), dim3(WG), kargs, 0, st);
   }
   if (e == hipSuccess) e = hipEventRecord(ev1, st);
-  GridCtl hg;
-  std::string hteams((size_t)nteams * sizeof(TeamCtl), '\0');
-  if (e == hipSuccess) e = hipMemcpyAsync(&hg, g->ctl.p, sizeof(GridCtl), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(&hteams[0], (char*)g->ctl.p + sizeof(GridCtl), hteams.size(), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   float ms = 0;
   if (e == hipSuccess) (void)hipEventElapsedTime(&ms, ev0, ev1);
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
   if (e != hipSuccess) return fail(from_hip(e), std::string("solve: ") + hipGetErrorString(e));
-  if (hg.abort_flag) return fail(SSSP_ERR_DEVICE, "grid barrier timed out (workgroups not co-resident?)");
-  bool step_limit = false;
-  for (uint32_t t = 0; t < nteams; ++t) {
-    TeamCtl tc;
-    std::memcpy(&tc, &hteams[(size_t)t * sizeof(TeamCtl)], sizeof(TeamCtl));
-    step_limit |= (tc.status & ST_STEP_LIMIT) != 0;
-    if (stats) {
-      stats->steps += tc.st_steps;
-      stats->extracted += tc.st_extracted;
-      stats->edges_relaxed += tc.st_edges;
-      stats->writemin_success += tc.st_success;
-      stats->dense_steps += tc.st_dense;
-      stats->sampled_steps += tc.st_sampled;
-      stats->queue_dense += tc.st_qdense;
-      stats->queue_list += tc.st_qlist;
-      stats->list_appends += tc.st_appends;
-      if (t == 0) {
-        for (int k = 0; k < 4; ++k) stats->phase_ms[k] = (double)tc.phase_ticks[k] / (double)g->tick_khz;
-        stats->relax_wg_ms[0] = (double)tc.relax_busy_max / (double)g->tick_khz;
-        stats->relax_wg_ms[1] = (double)tc.relax_busy_sum / (double)geo.T / (double)g->tick_khz;
-      }
-    }
-  }
-  if (stats) {
-    stats->device_ms = ms;
-    stats->teams = nteams;
-  }
+  bool aborted = false, step_limit = false;
+  sssp_status cs = collect_stats(g, L, st, stats, aborted, step_limit);
+  if (cs != SSSP_OK) return cs;
+  if (stats) stats->device_ms = ms;
+  if (aborted) return fail(SSSP_ERR_DEVICE, "grid barrier timed out (workgroups not co-resident?)");
   if (step_limit) return fail(SSSP_ERR_STEP_LIMIT, "max_steps reached with a non-empty queue");
   return SSSP_OK;
+}
+
+sssp_status sssp_row_hash(const uint64_t* dist, int64_t n, void* stream, uint64_t* hash) {
+  last_error().clear();
+  if (!dist || !hash || n < 0) return fail(SSSP_ERR_INVALID_ARGUMENT, "dist or hash is NULL, or n < 0");
+  hipStream_t st = (hipStream_t)stream;
+  DevBuf acc;
+  SSSP_HIP_TRY(acc.alloc(8, st));
+  hipError_t e = hipMemsetAsync(acc.p, 0, 8, st);
+  if (e == hipSuccess && n > 0) {
+    row_hash_kernel<<<1024, 256, 0, st>>>((const ull*)dist, (ull)n, (ull*)acc.p);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(hash, acc.p, 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  acc.release(st);
+  if (e != hipSuccess) return fail(from_hip(e), std::string("row hash: ") + hipGetErrorString(e));
+  return SSSP_OK;
+}
+
+sssp_status sssp_server_start(const sssp_graph* gc, const sssp_params* params, uint64_t* dist_rows, uint32_t rows,
+                              uint32_t ring_capacity, uint32_t flags, uint32_t idle_ms, void* stream,
+                              sssp_server** out) {
+  last_error().clear();
+  if (!out) return fail(SSSP_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (!gc || !dist_rows || rows == 0 || ring_capacity == 0)
+    return fail(SSSP_ERR_INVALID_ARGUMENT, "graph or dist_rows is NULL, or rows / ring_capacity is 0");
+  if (flags & ~SSSP_SERVE_HASH) return fail(SSSP_ERR_INVALID_ARGUMENT, "unknown server flags");
+  if (gc->serving) return fail(SSSP_ERR_INVALID_ARGUMENT, "a server is already running on this graph");
+  sssp_graph* g = const_cast<sssp_graph*>(gc);
+  sssp_server* s = new (std::nothrow) sssp_server;
+  if (!s) return fail(SSSP_ERR_OUT_OF_MEMORY, "server");
+  sssp_status ps = check_params(params, s->L.p, s->L.tu);
+  if (ps != SSSP_OK) {
+    delete s;
+    return ps;
+  }
+  // Half the co-resident slots by default, leaving room for other kernels
+  // (copies, checksums, a second server).
+  if (!s->L.p.tuning || s->L.p.tuning->blocks_per_cu == 0) s->L.tu.blocks_per_cu = 2;
+  if (s->L.p.trace || s->L.p.extract_counts || s->L.p.max_steps) {
+    delete s;
+    return fail(SSSP_ERR_INVALID_ARGUMENT, "trace, extract_counts and max_steps are not available when serving");
+  }
+  s->g = g;
+  s->caller = (hipStream_t)stream;
+  s->n = (uint64_t)g->n;
+  s->rows = rows;
+  s->cap = ring_capacity;
+  s->row_ticket.assign(rows, 0);
+  auto cleanup = [&](sssp_status st) {
+    if (s->req) (void)hipHostFree(s->req);
+    if (s->words) (void)hipHostFree(s->words);
+    if (s->st) (void)hipStreamDestroy(s->st);
+    if (s->ev0) (void)hipEventDestroy(s->ev0);
+    if (s->ev1) (void)hipEventDestroy(s->ev1);
+    delete s;
+    return st;
+  };
+  {
+    int occ = 0;
+    hipError_t e = hipSetDevice(g->device);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, stepping_kernel, WG, 0);
+    if (e != hipSuccess) return cleanup(fail(from_hip(e), hipGetErrorString(e)));
+    const uint32_t G = std::max(1u, std::min<uint32_t>(s->L.tu.blocks_per_cu, (uint32_t)std::max(occ, 1))) *
+                       (uint32_t)g->cus;
+    // Default: teams of 16 workgroups (a power of two count, at least 8).
+    uint32_t t = 8;
+    while (t * 2 <= G / 16 && G % (t * 2) == 0) t *= 2;
+    sssp_status ls = prepare_launch(g, s->L, G % 8 == 0 ? t : 1, dist_rows, s->caller);
+    if (ls != SSSP_OK) return cleanup(ls);
+  }
+  {
+    // HIP spreads streams over a few shared hardware queues, and a queue runs
+    // its kernels one after another: a persistent launch would hold back
+    // whatever shares its queue (another server, a copy of a finished row).
+    // A stream with a CU mask gets a queue of its own; the mask keeps every
+    // compute unit.
+    std::vector<uint32_t> mask(((size_t)g->cus + 31) / 32, 0xffffffffu);
+    hipError_t e = hipExtStreamCreateWithCUMask(&s->st, (uint32_t)mask.size(), mask.data());
+    hipEvent_t ready = nullptr;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ready, s->caller);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s->st, ready, 0);
+    if (ready) (void)hipEventDestroy(ready);
+    if (e != hipSuccess) return cleanup(fail(from_hip(e), std::string("server stream: ") + hipGetErrorString(e)));
+  }
+  // Host ring: requests, then the control words, in one coherent pinned
+  // allocation (device loads and stores reach it directly).
+  const size_t req_bytes = (size_t)s->cap * 8, words = 2 + (size_t)s->cap + 2 * (size_t)rows;
+  {
+    hipError_t e = hipHostMalloc((void**)&s->req, req_bytes, hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&s->words, words * 8, hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipEventCreate(&s->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&s->ev1);
+    if (e != hipSuccess) return cleanup(fail(from_hip(e), std::string("server ring: ") + hipGetErrorString(e)));
+  }
+  std::memset(s->req, 0, req_bytes);
+  std::memset(s->words, 0, words * 8);
+  s->posted = s->words;
+  s->closed = reinterpret_cast<uint32_t*>(s->words + 1);
+  s->ack = s->words + 2;
+  s->done = s->ack + s->cap;
+  s->hashes = s->done + rows;
+
+  KArgs& a = s->L.a;
+  a.n_src = 0;
+  a.serve = 1;
+  a.hash = (flags & SSSP_SERVE_HASH) ? 1u : 0u;
+  a.req = s->req;
+  a.posted = s->posted;
+  a.closed = s->closed;
+  a.ack = s->ack;
+  a.done = s->done;
+  a.hashes = s->hashes;
+  a.ring_cap = s->cap;
+  a.nrows = rows;
+  a.idle_ticks = g->tick_khz * (uint64_t)(idle_ms ? idle_ms : 60000);
+  a.tlimit += a.idle_ticks;  // team members wait at the claim barrier while a request is awaited
+  hipError_t e = stage_launch(g, s->L, s->st);
+  if (e == hipSuccess) e = hipEventRecord(s->ev0, s->st);
+  if (e == hipSuccess) {
+    // A plain launch: a cooperative one may wait for other cooperative
+    // launches, and servers on several graphs run side by side. The grid fits
+    // when the servers' blocks_per_cu sum to at most the occupancy; otherwise
+    // the first barrier times out and the server stops with an error.
+    const KArgs* dargs = (const KArgs*)g->args.p;
+    hipLaunchKernelGGL(stepping_kernel, dim3(s->L.G), dim3(WG), 0, s->st, dargs);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(s->ev1, s->st);
+  if (e != hipSuccess) return cleanup(fail(from_hip(e), std::string("server launch: ") + hipGetErrorString(e)));
+  g->serving = true;
+  *out = s;
+  return SSSP_OK;
+}
+
+sssp_status sssp_server_submit(sssp_server* s, int32_t source, uint32_t row, uint64_t* ticket) {
+  last_error().clear();
+  if (!s) return fail(SSSP_ERR_INVALID_ARGUMENT, "server is NULL");
+  if (s->stopped) return fail(SSSP_ERR_INVALID_ARGUMENT, "server is stopped");
+  if (source < 0 || (uint64_t)source >= s->n)
+    return fail(SSSP_ERR_INVALID_ARGUMENT, "source " + std::to_string(source) + " out of range");
+  if (row >= s->rows) return fail(SSSP_ERR_INVALID_ARGUMENT, "row " + std::to_string(row) + " out of range");
+  if (s->row_ticket[row]) return fail(SSSP_ERR_INVALID_ARGUMENT, "row " + std::to_string(row) + " is busy");
+  const uint64_t t = s->next_ticket;
+  const uint64_t e = t % s->cap;
+  // The entry is free once the kernel has taken the request that held it.
+  if (t >= s->cap && __atomic_load_n(&s->ack[e], __ATOMIC_ACQUIRE) != t - s->cap + 1)
+    return fail(SSSP_ERR_INVALID_ARGUMENT, "ring full");
+  if (hipEventQuery(s->ev1) == hipSuccess)
+    return fail(SSSP_ERR_DEVICE, "the server launch has ended (idle limit reached or an error)");
+  ++s->next_ticket;
+  s->req[2 * e] = source;
+  s->req[2 * e + 1] = (int32_t)row;
+  __atomic_store_n(s->posted, t + 1, __ATOMIC_RELEASE);
+  s->row_ticket[row] = t + 1;
+  s->busy_rows.push_back(row);
+  if (ticket) *ticket = t;
+  return SSSP_OK;
+}
+
+sssp_status sssp_server_poll(sssp_server* s, uint64_t* tickets, uint64_t* hashes, uint32_t max, uint32_t* count) {
+  last_error().clear();
+  if (!s || !count || (max && !tickets)) return fail(SSSP_ERR_INVALID_ARGUMENT, "server, tickets or count is NULL");
+  uint32_t c = 0;
+  for (size_t i = 0; i < s->busy_rows.size() && c < max;) {
+    const uint32_t row = s->busy_rows[i];
+    const uint64_t t1 = s->row_ticket[row];
+    if (__atomic_load_n(&s->done[row], __ATOMIC_ACQUIRE) == t1) {
+      tickets[c] = t1 - 1;
+      if (hashes) hashes[c] = __atomic_load_n(&s->hashes[row], __ATOMIC_RELAXED);
+      ++c;
+      s->row_ticket[row] = 0;
+      s->busy_rows[i] = s->busy_rows.back();
+      s->busy_rows.pop_back();
+    } else {
+      ++i;
+    }
+  }
+  *count = c;
+  return SSSP_OK;
+}
+
+sssp_status sssp_server_stop(sssp_server* s, sssp_stats* stats) {
+  last_error().clear();
+  if (!s) return fail(SSSP_ERR_INVALID_ARGUMENT, "server is NULL");
+  if (!s->stopped) {
+    s->stopped = true;
+    __atomic_store_n(s->closed, 1u, __ATOMIC_RELEASE);
+    hipError_t e = hipStreamSynchronize(s->st);
+    std::memset(&s->final_stats, 0, sizeof(s->final_stats));
+    if (e != hipSuccess) {
+      s->stop_status = fail(from_hip(e), std::string("server: ") + hipGetErrorString(e));
+    } else {
+      bool aborted = false, step_limit = false;
+      s->stop_status = collect_stats(s->g, s->L, s->st, &s->final_stats, aborted, step_limit);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, s->ev0, s->ev1);
+      s->final_stats.device_ms = ms;
+      if (s->stop_status == SSSP_OK && aborted)
+        s->stop_status = fail(SSSP_ERR_DEVICE, "server barrier or request wait timed out");
+    }
+    s->g->serving = false;
+  }
+  if (stats) *stats = s->final_stats;
+  return s->stop_status;
+}
+
+sssp_status sssp_server_destroy(sssp_server* s) {
+  if (!s) return SSSP_OK;
+  sssp_status st = SSSP_OK;
+  if (!s->stopped) st = sssp_server_stop(s, nullptr);
+  (void)hipHostFree(s->req);
+  (void)hipHostFree(s->words);
+  (void)hipStreamDestroy(s->st);
+  (void)hipEventDestroy(s->ev0);
+  (void)hipEventDestroy(s->ev1);
+  delete s;
+  return st;
 }
 
 }  // extern "C"
