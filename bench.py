@@ -50,6 +50,9 @@ WORKLOADS = {
                 "uniform over all vertices, solved together in one launch; rule and parameters autotuned",
 }
 BATCHED = {"knn10000": 64}
+WORKLOADS["serve"] = ("serving: R-MAT scale 22 (edge factor 16, w ~ U[1, 2^18)) and a 2000x2000 road-like grid "
+                      "(road recipe) both resident; each query picks R-MAT with probability 0.7, else the grid, and "
+                      "a uniform source in that graph's largest component; Poisson arrivals")
 
 
 def log(*a):
@@ -301,6 +304,194 @@ def run_batched(args, torch, sp, w):
     return res
 
 
+def np_row_hash(d: np.ndarray) -> int:
+    """Checksum of a distance row, as sssp_row_hash defines it (for oracle rows)."""
+    v = np.arange(d.size, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = d.astype(np.uint64) ^ (v * np.uint64(0x9E3779B97F4A7C15))
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+        return int(z.sum(dtype=np.uint64))
+
+
+def run_serve(args, torch, sp):
+    """Continuous-batching servers (one persistent launch per graph, requests
+    joining as teams free up) against a one-query-at-a-time loop of plain
+    solves, on the same query trace: closed loop (all queries queued at once)
+    for saturation throughput, then open loop with Poisson arrivals at 0.8 x
+    the plain loop's saturation rate."""
+    import graphgen
+    from paper_2105_06145_amd import autotune as at
+    side = torch.cuda.Stream()  # keep work off the NULL stream while servers run
+    torch.cuda.set_stream(side)
+    t0 = time.time()
+    gr = graphgen.rmat(22, 16, seed=5001)
+    gd = graphgen.road(2000, 2000, seed=5002)
+    graphs = [gr, gd]
+    lcc = [graphgen.largest_component(g) for g in graphs]
+    log(f"serve graphs: rmat22 n={gr.n} m={gr.m}, road2000 n={gd.n} m={gd.m} ({time.time() - t0:.1f}s)")
+    G = [sp.Graph.from_csr(gr.offsets, gr.targets, gr.weights),
+         sp.Graph.from_csr(gd.offsets, gd.targets, gd.weights, reorder=False)]
+    nq = args.queries
+    rng = np.random.default_rng(5003)
+    which = (rng.random(nq) >= 0.7).astype(np.int64)  # 0: R-MAT (p = 0.7), 1: grid
+    pools = [np.flatnonzero(m) for m in lcc]
+    src = np.array([int(pools[k][rng.integers(0, pools[k].size)]) for k in which], dtype=np.int64)
+    gaps = rng.exponential(1.0, nq)  # unit-rate Poisson process, scaled below
+
+    # Parameters: tuned on a batch of the trace's sources per graph (served),
+    # and on 8 single queries per graph (plain).
+    cfg_s, cfg_p = [], []
+    for k in (0, 1):
+        ks = [int(x) for x in src[which == k][:32]]
+        tb = at.Tuner(budget_s=args.tune_budget / 2)
+        cfg_s.append(tb.tune(G[k], ks, rules=("rho",) if k == 0 else ("delta",)))
+
+        def plain_measure(cfg, k=k, ks=ks):
+            kw = {x: cfg[x] for x in ("rho", "delta") if x in cfg}
+            tun = {**(cfg.get("tuning") or {}), "teams": 1}
+            return sum(sp.solve(G[k], [s], rule=cfg["rule"], tuning=tun, **kw)[1]["device_ms"] for s in ks[:8])
+        cfg_p.append(at.Tuner(budget_s=args.tune_budget / 2, measure=plain_measure).search(
+            G[k].n, 1, G[k].summary["weight_q10_50_90"][1] or 1, rules=("rho",) if k == 0 else ("delta",)))
+        log(f"graph {k}: served {cfg_s[k]}, plain {cfg_p[k]}")
+
+    def params(cfg):
+        return {x: cfg[x] for x in ("rule", "rho", "delta") if x in cfg}
+
+    out1 = [torch.empty((1, g.n), dtype=torch.int64, device="cuda") for g in graphs]
+
+    def plain_loop(arrive):
+        """One query at a time, whole grid each; returns (latencies, hashes, makespan)."""
+        lat = np.zeros(nq)
+        hashes = [0] * nq
+        start = time.perf_counter()
+        for i in range(nq):
+            k = int(which[i])
+            now = time.perf_counter() - start
+            if now < arrive[i]:
+                time.sleep(arrive[i] - now)
+            tun = {**(cfg_p[k].get("tuning") or {}), "teams": 1}
+            sp.solve(G[k], [int(src[i])], tuning=tun, out=out1[k], stream=side, **params(cfg_p[k]))
+            hashes[i] = sp.row_hash(out1[k][0], stream=side)
+            lat[i] = time.perf_counter() - start - arrive[i]
+            if (i + 1) % 50 == 0:
+                log(f"  plain: {i + 1}/{nq} queries, {time.perf_counter() - start:.1f}s")
+        return lat, hashes, time.perf_counter() - start
+
+    nrows = args.rows
+    serve_teams = [int(x) for x in args.serve_teams.split(",")]
+    rows = [torch.empty((nrows, g.n), dtype=torch.int64, device="cuda") for g in graphs]
+
+    def served_loop(arrive):
+        """Both graphs' servers running; queries admitted in arrival order as
+        rows free up; returns (latencies, hashes, makespan, stats)."""
+        servers = [sp.Server(G[k], rows[k], tuning={**(cfg_s[k].get("tuning") or {}), "blocks_per_cu": 2,
+                                                    "teams": serve_teams[k]}, hash_rows=True,
+                             ring_capacity=2 * nrows, stream=side, **params(cfg_s[k])) for k in (0, 1)]
+        free = [list(range(nrows)), list(range(nrows))]
+        ticket = [{}, {}]
+        lat = np.zeros(nq)
+        hashes = [0] * nq
+        waiting = [[], []]  # arrived, not yet admitted (per graph, FIFO)
+        nxt = done = 0
+        start = time.perf_counter()
+        last_log = start
+        while done < nq:
+            if time.perf_counter() - last_log > 5.0:
+                last_log = time.perf_counter()
+                log(f"  served: {done}/{nq} queries, {last_log - start:.1f}s")
+            now = time.perf_counter() - start
+            while nxt < nq and arrive[nxt] <= now:
+                waiting[int(which[nxt])].append(nxt)
+                nxt += 1
+            for k in (0, 1):
+                S = servers[k]
+                while waiting[k] and free[k]:
+                    i = waiting[k].pop(0)
+                    r = free[k].pop()
+                    ticket[k][S.submit(int(src[i]), r)] = (i, r)
+                for t, h in S.poll():
+                    i, r = ticket[k].pop(t)
+                    lat[i] = time.perf_counter() - start - arrive[i]
+                    hashes[i] = h
+                    free[k].append(r)
+                    done += 1
+        makespan = time.perf_counter() - start
+        stats = [S.stop() for S in servers]
+        for S in servers:
+            S.close()
+        return lat, hashes, makespan, stats
+
+    # Closed loop: everything queued at t = 0.
+    zero = np.zeros(nq)
+    lat_p0, hash_p, span_p0 = plain_loop(zero)
+    rate_plain = nq / span_p0
+    log(f"plain closed loop: {span_p0:.2f}s, {rate_plain:.1f} q/s")
+    lat_s0, hash_s0, span_s0, _ = served_loop(zero)
+    log(f"served closed loop: {span_s0:.2f}s, {nq / span_s0:.1f} q/s")
+    # Open loop at 0.8 x the plain saturation rate.
+    lam = 0.8 * rate_plain
+    arrive = np.cumsum(gaps) / lam
+    lat_p1, hash_p1, span_p1 = plain_loop(arrive)
+    lat_s1, hash_s1, span_s1, sstats = served_loop(arrive)
+    log(f"open loop lambda={lam:.1f}/s: plain p50 {np.median(lat_p1) * 1e3:.1f} ms, served p50 "
+        f"{np.median(lat_s1) * 1e3:.1f} ms")
+    same = all(hash_p[i] == hash_s0[i] == hash_p1[i] == hash_s1[i] for i in range(nq))
+    # Oracle sample.
+    checked = 0
+    if not args.no_cpu_baseline:
+        import oracle
+        c0 = oracle.now()
+        for k in (0, 1):
+            for i in np.flatnonzero(which == k)[:args.oracle_sample]:
+                d = oracle.dijkstra(graphs[k].offsets, graphs[k].targets, graphs[k].weights, int(src[i]))
+                assert np_row_hash(d) == hash_s1[i], f"query {i}: served row differs from the oracle"
+                checked += 1
+        csecs = oracle.now() - c0
+    edges_served = sum(st["edges_relaxed"] for st in sstats)
+
+    def pct(x, q):
+        return round(float(np.percentile(x, q)) * 1e3, 3)
+
+    res = {
+        "metric": METRIC,
+        "value": round(nq / span_s1, 2),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": nq,
+        "warmup": 0,
+        "ms_per_step": round(span_s1 * 1e3 / nq, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["serve"], "queries": nq, "rows_per_graph": nrows,
+                   "server_teams": serve_teams, "server_blocks_per_cu": 2,
+                   "served": [params(c) | {"tuning": c.get("tuning")} for c in cfg_s],
+                   "plain": [params(c) | {"tuning": c.get("tuning")} for c in cfg_p]},
+        "closed_loop": {"plain_qps": round(rate_plain, 2), "served_qps": round(nq / span_s0, 2),
+                        "speedup": round(span_p0 / span_s0, 3)},
+        "open_loop": {"lambda_qps": round(lam, 2),
+                      "plain_ms": {"p50": pct(lat_p1, 50), "p99": pct(lat_p1, 99)},
+                      "served_ms": {"p50": pct(lat_s1, 50), "p99": pct(lat_s1, 99)},
+                      "by_graph_p50_ms": {"rmat": [pct(lat_p1[which == 0], 50), pct(lat_s1[which == 0], 50)],
+                                          "grid": [pct(lat_p1[which == 1], 50), pct(lat_s1[which == 1], 50)],
+                                          "order": ["plain", "served"]},
+                      "served_gteps": round(edges_served / (span_s1 * 1e9), 4)},
+        "same_alone_and_in_the_mix": same,
+        "oracle_checked": checked,
+        "roofline": None,
+        "cpu_baseline": None if args.no_cpu_baseline else {
+            "value": round(checked / csecs, 3), "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": f"{checked} of the trace's queries, one binary-heap Dijkstra each ({csecs:.1f} s, 1 thread)"},
+    }
+    for g in G:
+        g.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -312,6 +503,12 @@ def main():
     ap.add_argument("--sweep", default="", metavar="LOG2_LIST",
                     help="e.g. 16,17,18,19,20,21,22: time 3 solves per rho first and use the fastest")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--queries", type=int, default=600, help="serving: queries in the trace")
+    ap.add_argument("--rows", type=int, default=64, help="serving: result rows (admission slots) per graph")
+    ap.add_argument("--serve-teams", default="8,32",
+                    help="serving: teams of the R-MAT and grid servers (each server has 2 workgroups per CU: "
+                         "8 teams = 64 workgroups per query, 32 = 16)")
+    ap.add_argument("--oracle-sample", type=int, default=4, help="serving: queries per graph checked by the oracle")
     ap.add_argument("--tune-budget", type=float, default=20.0,
                     help="seconds of parameter search per mode for the batched workload (0 = workload defaults)")
     ap.add_argument("--cpu-settle-cap", type=int, default=0,
@@ -346,6 +543,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
+    if args.workload == "serve":
+        print(json.dumps(run_serve(args, torch, sp)), flush=True)
+        return
     t0 = time.time()
     w = graphgen.workload(args.workload, sources=BATCHED.get(args.workload, 1))
     log(f"workload {args.workload}: n={w.graph.n} m={w.graph.m} sources={len(w.sources)} "

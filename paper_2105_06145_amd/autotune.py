@@ -6,9 +6,11 @@ steps and the redundant work, and the best values depend on the graph (the
 paper picks rho per graph and motivates a rule that needs no preprocessing).
 This module searches them by timing real solves on the device:
 
-  1. the rule parameter: rho over powers of four from 2^8 up to n, then the
-     neighbouring powers of two; Delta over the median arc weight times
-     powers of four, then the neighbouring powers of two;
+  1. the rule parameter, from large to small (large values mean few steps,
+     small ones many; the time is taken to fall and then rise along the way,
+     so the sweep stops once two values in a row are slower than the best):
+     rho over powers of four from n down to 2^8, Delta over the median arc
+     weight times powers of four; then the neighbouring powers of two;
   2. for batches, the number of teams the persistent grid is split into;
   3. the hub-degree threshold, then the explicit-list switch.
 
@@ -35,13 +37,15 @@ def batch_class(nsrc: int) -> int:
 
 
 def rho_candidates(n: int) -> list[int]:
+    """Powers of four from about n down to 2^8, largest first."""
     top = max(8, (max(n, 2) - 1).bit_length())
-    return [1 << k for k in range(8, top + 1, 2)]
+    return [1 << k for k in range(top - (top - 8) % 2, 7, -2)]
 
 
 def delta_candidates(w_median: int) -> list[int]:
+    """The median arc weight times 4^5 down to 4^-1, largest first."""
     base = max(1, int(w_median))
-    return [max(1, base << k) if k >= 0 else max(1, base >> -k) for k in range(-2, 11, 2)]
+    return [max(1, base << k) if k >= 0 else max(1, base >> -k) for k in range(10, -3, -2)]
 
 
 def team_candidates(nsrc: int, grid: int = 1024) -> list[int]:
@@ -125,10 +129,12 @@ class Tuner:
                 self._eval({"rule": rule, "tuning": dict(base_tuning)}, best)
                 continue
             scores = {}
+            worse = 0
             for v in cands:
-                if out_of_time() and best[0] is not None:
+                if (out_of_time() and best[0] is not None) or worse >= 2:
                     break
                 scores[v] = self._eval({"rule": rule, name: v, "tuning": dict(base_tuning)}, best)
+                worse = worse + 1 if scores[v] > min(scores.values()) else 0
             if not scores:
                 continue
             v0 = min(scores, key=scores.get)

@@ -25,9 +25,10 @@ def cost_model(cfg):
 
 
 def test_candidates():
-    assert at.rho_candidates(1 << 20) == [1 << k for k in range(8, 21, 2)]
+    assert at.rho_candidates(1 << 20) == [1 << k for k in range(20, 7, -2)]
+    assert at.rho_candidates((1 << 21) + 5) == [1 << k for k in range(22, 7, -2)]
     assert at.rho_candidates(5) == [256]
-    assert at.delta_candidates(1000) == [250, 1000, 4000, 16000, 64000, 256000, 1024000]
+    assert at.delta_candidates(1000) == [1024000, 256000, 64000, 16000, 4000, 1000, 250]
     assert at.team_candidates(64) == [8, 16, 32, 64]
     assert at.team_candidates(3) == [8]
     assert [at.batch_class(x) for x in (1, 2, 8, 9, 64, 65)] == [1, 8, 8, 16, 64, 128]
@@ -41,6 +42,20 @@ def test_search_finds_the_minimum_of_the_model():
     assert cfg.get("tuning", {}).get("list_divisor", 64) == 64
     assert cfg["ms"] == pytest.approx(9.5)
     assert cfg["evaluations"] == len(tu.history)
+
+
+def test_sweep_stops_after_two_slower_values():
+    calls = []
+
+    def model(cfg):
+        calls.append(cfg.get("rho"))
+        return abs(math.log2(cfg["rho"]) - 18) if "rho" in cfg else 1.0
+
+    at.Tuner(measure=model).search(n=1 << 24, nsrc=1, w_median=1, rules=("rho",))
+    sweep = [c for c in calls if c is not None]
+    # 2^24, 2^22, 2^20, 2^18 (best), 2^16, 2^14 (second slower: stop), then 2^17 and 2^19.
+    assert sweep[:6] == [1 << 24, 1 << 22, 1 << 20, 1 << 18, 1 << 16, 1 << 14]
+    assert set(sweep[6:8]) == {1 << 17, 1 << 19}
 
 
 def test_search_single_source_has_no_teams_and_obeys_budget():
