@@ -103,6 +103,16 @@ typedef struct {
                              this many teams of workgroups, each solving one source at a time
                              (must divide the grid size). 0 = 1 for a single source, else a
                              power of two >= 8, about one team per source */
+  uint32_t local_budget;  /* local expansion (large neighbour sets, Sec. 6): in super-sparse
+                             steps a workgroup relaxes the vertices its WriteMins bring to
+                             at most theta itself, hop after hop, up to this many per step,
+                             instead of returning them to Q (default 4096; 0xFFFFFFFF = off;
+                             always off with SSSP_SOLVE_SNAPSHOT_KEYS) */
+  uint32_t super_sparse_degree; /* steps on the explicit list whose previous step relaxed fewer
+                             arcs than this per vertex count as super-sparse (default 10;
+                             the first step compares the graph's average out-degree) */
+  uint32_t reserved0;
+  uint32_t reserved1;
 } sssp_tuning;
 
 /* One record per step, written when params.trace is set. */
@@ -165,6 +175,7 @@ typedef struct {
   uint64_t queue_dense;      /* sum of |Q| over steps whose Extract scanned the bitmap */
   uint64_t queue_list;       /* sum of |Q| over steps whose Extract read the explicit list */
   uint64_t list_appends;     /* entries written to explicit lists (kept and new members) */
+  uint64_t local_vertices;   /* vertices relaxed by local expansion (not counted in extracted) */
 } sssp_stats;
 
 typedef struct sssp_graph sssp_graph; /* opaque */

@@ -51,7 +51,9 @@ class sssp_tuning(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_uint32), ("hub_degree", ctypes.c_uint32),
                 ("chunk_edges", ctypes.c_uint32), ("list_divisor", ctypes.c_uint32),
                 ("sample_cap", ctypes.c_uint32), ("probe_cap", ctypes.c_uint32),
-                ("no_filter", ctypes.c_uint32), ("teams", ctypes.c_uint32)]
+                ("no_filter", ctypes.c_uint32), ("teams", ctypes.c_uint32),
+                ("local_budget", ctypes.c_uint32), ("super_sparse_degree", ctypes.c_uint32),
+                ("reserved0", ctypes.c_uint32), ("reserved1", ctypes.c_uint32)]
 
 
 class sssp_step_record(ctypes.Structure):
@@ -73,7 +75,7 @@ class sssp_stats(ctypes.Structure):
                 ("sampled_steps", ctypes.c_uint64), ("device_ms", ctypes.c_double),
                 ("phase_ms", ctypes.c_double * 4), ("relax_wg_ms", ctypes.c_double * 2),
                 ("teams", ctypes.c_uint64), ("queue_dense", ctypes.c_uint64), ("queue_list", ctypes.c_uint64),
-                ("list_appends", ctypes.c_uint64)]
+                ("list_appends", ctypes.c_uint64), ("local_vertices", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}

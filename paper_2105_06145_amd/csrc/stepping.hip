@@ -75,6 +75,7 @@ constexpr int UNROLL = 4;       // arcs / list entries per lane per iteration
 constexpr int BATCH = 4;        // queue members per lane per round in bitmap scans
 constexpr int MAX_XCC = 16;
 constexpr int BLOCK_WORDS = 4;  // bitmap words per ownership block (256 vertices)
+constexpr int LQ = 1024;        // local-expansion list capacity per round (LDS)
 
 // ---------------------------------------------------------------------------
 // Control blocks.
@@ -88,7 +89,8 @@ struct alignas(128) StepSlot {
   ull min_next;     // min key over the next queue
   ull edges;        // arcs relaxed
   ull successes;    // successful WriteMins
-  ull pad[8];
+  ull local_v;      // vertices relaxed by local expansion
+  ull pad[7];
 };
 
 struct alignas(128) Line {
@@ -104,7 +106,7 @@ struct TeamCtl {
   ull query;   // index of the source being solved
   ull status;  // 1: step limit reached on some query
   ull st_steps, st_extracted, st_edges, st_success, st_dense, st_sampled;
-  ull st_qdense, st_qlist, st_appends;
+  ull st_qdense, st_qlist, st_appends, st_local;
   ull relax_busy_max, relax_busy_sum;
   ull phase_ticks[4];  // init, threshold, extract, relax (the team's first workgroup)
   // Serving: the current request and the one still to be published.
@@ -141,11 +143,12 @@ struct alignas(64) Part {
   ull fresh;    // new queue members
   ull minnew;   // min successful WriteMin value
   ull busy;     // wall-clock ticks this workgroup spent in Relax
-  ull pad;
+  ull local;    // vertices relaxed by local expansion
 };
 
 struct KArgs {
   int64_t n;
+  uint64_t m;
   uint64_t nwords;
   const int64_t* off;
   const ull* edges;     // (weight << 32) | target
@@ -180,6 +183,8 @@ struct KArgs {
   uint32_t probe_cap;
   uint32_t filter;
   uint32_t snapshot;  // relax with the keys at extraction
+  uint32_t local_budget;  // vertices a workgroup may relax by local expansion per step (0: off)
+  uint32_t super_sparse;  // local expansion in list steps below this average out-degree
   // Serving mode: requests come from a ring in host memory instead of srcs.
   uint32_t serve;
   uint32_t hash;               // add each finished row's checksum to its ring entry
@@ -204,6 +209,8 @@ struct Shared {
   uint32_t wsum[WAVES];
   ull red[WAVES * 4];
   ull bcast[4];
+  int32_t lq[2][LQ];  // local expansion: this round's vertices and the next round's
+  uint32_t lqn[2];
   int last;
   int abort;
 };
@@ -548,17 +555,17 @@ __device__ __noinline__ void push_hub(const KArgs& a, ull* H, StepSlot* S, int32
   }
 }
 
-// Relax one arc (S3 + S4). Returns true when v became a new queue member.
+// WriteMin(delta[v], nd) (S3). Returns true when it lowered delta[v].
 // Filter: a plain read of delta[v] (possibly stale, but never smaller than
 // the current value) showing nd >= delta[v] means the WriteMin cannot succeed,
 // so the atomic is skipped.
-__device__ __forceinline__ bool relax_arc(const KArgs& a, ull* dist, ull* bitmap, ull& succ, ull& minnew, int32_t v,
-                                          ull nd) {
+__device__ __forceinline__ bool writemin(const KArgs& a, ull* dist, int32_t v, ull nd) {
   if (a.filter && !(nd < ld_plain(&dist[v]))) return false;
-  const ull old = atom_min(&dist[v], nd);
-  if (!(nd < old)) return false;
-  ++succ;
-  minnew = umin(minnew, nd);
+  return nd < atom_min(&dist[v], nd);
+}
+
+// Update(v) (S4): set v's flag; true when v is new to Q.
+__device__ __forceinline__ bool mark(ull* bitmap, int32_t v) {
   const ull bit = 1ull << (v & 63);
   return !(atom_or(&bitmap[v >> 6], bit) & bit);
 }
@@ -758,14 +765,28 @@ __device__ __noinline__ ExtractOut phase_extract_list(const KArgs& a, const ull*
 }
 
 struct RelaxAcc {
-  ull edges, succ, fresh, minnew;
+  ull edges, succ, fresh, minnew, local;
 };
 
-// Relax UNROLL arcs per lane (ev = packed arc or INF, dd = key of its tail)
-// and append new queue members to the next list when it is being built.
+// Local expansion (the paper's large neighbour sets, Sec. 6): in a sparse
+// step, a vertex whose key a WriteMin lowers to at most theta is not put back
+// in Q but relaxed by the same workgroup later in the same step, round after
+// round from a list in LDS, until the list is empty or the workgroup has
+// relaxed `local_budget` vertices this way; what is left then goes to Q. One
+// step thus advances several hops without a grid barrier per hop.
+struct Local {
+  bool on;
+  uint32_t nxt;  // LDS list receiving this round's vertices
+  ull theta;
+};
+
+// Relax UNROLL arcs per lane (ev = packed arc or INF, dd = key of its tail):
+// WriteMin, then either the local list or Update, and the new queue members
+// to the next explicit list when it is being built.
 __device__ __forceinline__ void relax_batch(const KArgs& a, const Team& tm, ull* dist, StepSlot* S, int32_t* Lnext,
-                                            bool emit, RelaxAcc& acc, const ull (&ev)[UNROLL],
+                                            bool emit, RelaxAcc& acc, const Local& lx, const ull (&ev)[UNROLL],
                                             const ull (&dd)[UNROLL]) {
+  Shared& sh = g_sh;
   int32_t fv[UNROLL];
   unsigned mask = 0;
 #pragma unroll
@@ -773,7 +794,19 @@ __device__ __forceinline__ void relax_batch(const KArgs& a, const Team& tm, ull*
     fv[k] = (int32_t)(uint32_t)ev[k];
     if (ev[k] == INF) continue;
     ++acc.edges;
-    if (relax_arc(a, dist, tm.bitmap, acc.succ, acc.minnew, fv[k], dd[k] + (ev[k] >> 32))) {
+    const ull nd = dd[k] + (ev[k] >> 32);
+    if (!writemin(a, dist, fv[k], nd)) continue;
+    ++acc.succ;
+    // Hubs go to Q, where their arcs are split over the team.
+    if (lx.on && nd <= lx.theta && !((ld_plain(&a.hubmask[fv[k] >> 6]) >> (fv[k] & 63)) & 1ull)) {
+      const uint32_t slot = atomicAdd(&sh.lqn[lx.nxt], 1u);
+      if (slot < (uint32_t)LQ) {
+        sh.lq[lx.nxt][slot] = fv[k];
+        continue;
+      }
+    }
+    acc.minnew = umin(acc.minnew, nd);
+    if (mark(tm.bitmap, fv[k])) {
       ++acc.fresh;
       mask |= 1u << k;
     }
@@ -781,15 +814,60 @@ __device__ __forceinline__ void relax_batch(const KArgs& a, const Team& tm, ull*
   if (emit) list_append(a, S, Lnext, fv, mask);
 }
 
+// Relax the arcs of up to WG vertices (one per thread; u < 0 for none, du its
+// key) as one tile: degree prefix sums and row starts in LDS, then UNROLL
+// arcs per lane per round, consecutive lanes on consecutive arcs. Whole
+// workgroup, uniform call.
+__device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* dist, StepSlot* S, int32_t* Lnext,
+                                           bool emit, RelaxAcc& acc, const Local& lx, int32_t u, ull du) {
+  Shared& sh = g_sh;
+  const unsigned tid = threadIdx.x;
+  uint32_t deg = 0;
+  ull rb = 0;
+  if (u >= 0) {
+    rb = (ull)a.off[u];
+    deg = (uint32_t)((ull)a.off[u + 1] - rb);
+  }
+  uint32_t total;
+  const uint32_t excl = wg_scan(sh, deg, total);
+  sh.pre[tid] = excl;
+  sh.beg[tid] = rb;
+  sh.du[tid] = du;
+  __syncthreads();
+  for (uint32_t e0 = 0; e0 < total; e0 += WG * UNROLL) {
+    ull ev[UNROLL], dd[UNROLL];
+#pragma unroll
+    for (int k = 0; k < UNROLL; ++k) {
+      const uint32_t e = e0 + k * WG + tid;
+      ev[k] = INF;
+      dd[k] = 0;
+      if (e < total) {
+        int lo = 0;
+#pragma unroll
+        for (int step = WG / 2; step > 0; step >>= 1)
+          if (sh.pre[lo + step] <= e) lo += step;
+        ev[k] = a.edges[sh.beg[lo] + (e - sh.pre[lo])];
+        dd[k] = sh.du[lo];
+      }
+    }
+    relax_batch(a, tm, dist, S, Lnext, emit, acc, lx, ev, dd);
+  }
+  __syncthreads();
+}
+
 // S3 + S4: the team's hub chunks (strided over its workgroups), then this
-// workgroup's own extracted vertices. Writes the workgroup's partial counts.
-__device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S, int32_t* Lnext,
-                                         bool emit, ExtractOut ex) {
+// workgroup's own extracted vertices, then (local expansion) the rounds of
+// vertices they improved. Writes the workgroup's partial counts.
+__device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S, int32_t* Lnext, bool emit,
+                                         ExtractOut ex, bool local, ull theta) {
   const Team& tm = g_tm;
   Shared& sh = g_sh;
   const unsigned tid = threadIdx.x;
   const long long t_start = wall_clock64();
-  RelaxAcc acc{0, 0, 0, INF};
+  RelaxAcc acc{0, 0, 0, INF, 0};
+  Local lx{local, 0, theta};
+  if (tid < 2) sh.lqn[tid] = 0;
+  __syncthreads();
   const ull nH = ld_agent(&S->h_count);
   const ull CH = a.chunk_edges;
   for (ull item = tm.rank; item < nH; item += tm.T) {
@@ -808,45 +886,56 @@ __device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S,
         ev[k] = e < end ? a.edges[e] : INF;
         dd[k] = du;
       }
-      relax_batch(a, tm, dist, S, Lnext, emit, acc, ev, dd);
+      relax_batch(a, tm, dist, S, Lnext, emit, acc, lx, ev, dd);
     }
   }
-  for (uint32_t j0 = 0; j0 < ex.fcnt; j0 += WG) {
-    const uint32_t j = j0 + tid;
-    uint32_t deg = 0;
-    ull rb = 0, du = 0;
-    if (j < ex.fcnt) {
-      const int32_t u = tm.Fb[j];
-      rb = (ull)a.off[u];
-      deg = (uint32_t)((ull)a.off[u + 1] - rb);
-      du = a.snapshot ? tm.FDb[j] : ld_agent(&dist[u]);
-    }
-    uint32_t total;
-    const uint32_t excl = wg_scan(sh, deg, total);
-    sh.pre[tid] = excl;
-    sh.beg[tid] = rb;
-    sh.du[tid] = du;
-    __syncthreads();
-    for (uint32_t e0 = 0; e0 < total; e0 += WG * UNROLL) {
-      ull ev[UNROLL], dd[UNROLL];
-#pragma unroll
-      for (int k = 0; k < UNROLL; ++k) {
-        const uint32_t e = e0 + k * WG + tid;
-        ev[k] = INF;
-        dd[k] = 0;
-        if (e < total) {
-          int lo = 0;
-#pragma unroll
-          for (int step = WG / 2; step > 0; step >>= 1)
-            if (sh.pre[lo + step] <= e) lo += step;
-          ev[k] = a.edges[sh.beg[lo] + (e - sh.pre[lo])];
-          dd[k] = sh.du[lo];
-        }
+  // Round 0: this workgroup's extracted vertices. Later rounds (local
+  // expansion): LDS list `cur`, the vertices the previous round improved
+  // (capped at LQ; pushes beyond it went to Q).
+  uint32_t cnt = ex.fcnt, cur = 1;
+  ull done_local = 0;
+  for (bool first = true;; first = false) {
+    for (uint32_t j0 = 0; j0 < cnt; j0 += WG) {
+      const uint32_t j = j0 + tid;
+      int32_t u = -1;
+      ull du = 0;
+      if (j < cnt) {
+        u = first ? tm.Fb[j] : sh.lq[cur][j];
+        du = (first && a.snapshot) ? tm.FDb[j] : ld_agent(&dist[u]);
       }
-      relax_batch(a, tm, dist, S, Lnext, emit, acc, ev, dd);
+      relax_tile(a, tm, dist, S, Lnext, emit, acc, lx, u, du);
     }
+    if (!local) break;
+    cur = lx.nxt;
     __syncthreads();
+    cnt = min(sh.lqn[cur], (uint32_t)LQ);
+    if (cnt == 0) break;
+    {
+      if (done_local + cnt > a.local_budget) {
+        // Out of budget: the rest joins Q.
+        for (uint32_t j0 = 0; j0 < cnt; j0 += WG) {
+          const uint32_t j = j0 + tid;
+          int32_t v[1] = {-1};
+          unsigned m = 0;
+          if (j < cnt) {
+            v[0] = sh.lq[cur][j];
+            acc.minnew = umin(acc.minnew, ld_agent(&dist[v[0]]));
+            if (mark(tm.bitmap, v[0])) {
+              ++acc.fresh;
+              m = 1;
+            }
+          }
+          if (emit) list_append(a, S, Lnext, v, m);
+        }
+        break;
+      }
+      done_local += cnt;
+      if (tid == 0) sh.lqn[cur ^ 1u] = 0;
+      __syncthreads();
+      lx.nxt = cur ^ 1u;
+    }
   }
+  acc.local = done_local;
   ull xs = ex.x, mk = ex.minkept;
   wg_reduce4(sh, acc.edges, acc.succ, acc.fresh, acc.minnew);
   {
@@ -862,7 +951,7 @@ __device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S,
     p.fresh = acc.fresh;
     p.minnew = acc.minnew;
     p.busy = (ull)(wall_clock64() - t_start);
-    p.pad = 0;
+    p.local = acc.local;
     a.parts[blockIdx.x] = p;
   }
 }
@@ -876,7 +965,7 @@ __device__ __noinline__ void step_bookkeeping(const KArgs& a, StepSlot* S, ull t
   Shared& sh = g_sh;
   const unsigned tid = threadIdx.x;
   TeamCtl* tc = tm.ctl;
-  ull x = 0, e = 0, s = 0, f = 0, mn = INF, busy = 0, negbusy = INF;
+  ull x = 0, e = 0, s = 0, f = 0, mn = INF, busy = 0, negbusy = INF, lv = 0;
   for (ull r = tid; r < tm.T; r += WG) {
     const ull* p = reinterpret_cast<const ull*>(&a.parts[tm.id + r * a.nteams]);
     x += ld_agent(p + 0);
@@ -886,14 +975,12 @@ __device__ __noinline__ void step_bookkeeping(const KArgs& a, StepSlot* S, ull t
     f += ld_agent(p + 4);
     mn = umin(mn, ld_agent(p + 5));
     const ull bz = ld_agent(p + 6);
+    lv += ld_agent(p + 7);
     busy += bz;
     negbusy = umin(negbusy, ~bz);
   }
   wg_reduce4(sh, x, e, s, mn);
-  {
-    ull z0 = 0;
-    wg_reduce4(sh, f, busy, z0, negbusy);
-  }
+  wg_reduce4(sh, f, busy, lv, negbusy);
   if (tid < 16) {
     ull* z = reinterpret_cast<ull*>(&tc->slot[(t + 2) % 3]);
     z[tid] = 0ull;
@@ -904,6 +991,8 @@ __device__ __noinline__ void step_bookkeeping(const KArgs& a, StepSlot* S, ull t
     S->min_next = mn;
     S->edges = e;
     S->successes = s;
+    S->local_v = lv;
+    tc->st_local += lv;
     tc->st_steps += 1;
     tc->st_extracted += x;
     tc->st_edges += e;
@@ -1119,6 +1208,9 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
     }
 
     ull q = 1, minq = 0, idelta = 0, dense_steps = 0;
+    // Vertices relaxed and arcs of the previous step (before the first: the
+    // whole graph, so that the first step is super-sparse when the graph is).
+    ull prev_x = n, prev_e = a.m;
     bool list_valid = true;
 
     for (ull t = 0;; ++t) {
@@ -1177,7 +1269,10 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
       ph2 += lap();
 
       // ---- S3/S4: Relax + Update ----
-      phase_relax(a, dist, S, Lnext, emit, ex);
+      // Local expansion in super-sparse steps: list steps whose previous
+      // step relaxed fewer than super_sparse arcs per vertex on average.
+      const bool local = a.local_budget && !dense && prev_e < (ull)a.super_sparse * umin(prev_x, INF / 64);
+      phase_relax(a, dist, S, Lnext, emit, ex, local, theta);
       const unsigned flags = (dense ? 1u : 0u) | (emit ? 2u : 0u) | (sampled ? 4u : 0u);
       auto bookkeeping = [&]() { step_bookkeeping(a, S, t, q, theta, flags); };
       if (!team_sync(a, sh, tm, bookkeeping)) return;
@@ -1186,6 +1281,8 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
       // ---- S5: next queue state, identical in every workgroup of the team ----
       q = q - ld_agent(&S->x_total) + ld_agent(&S->fresh_total);
       minq = ld_agent(&S->min_next);
+      prev_x = ld_agent(&S->x_total) + ld_agent(&S->local_v);
+      prev_e = ld_agent(&S->edges);
       list_valid = emit && ld_agent(&S->list_next) <= a.lcap;
       if (dense) ++dense_steps;
     }
@@ -1242,6 +1339,8 @@ sssp_tuning default_tuning() {
   t.probe_cap = 1u << 16;
   t.no_filter = 0;
   t.teams = 0;
+  t.local_budget = 4096;
+  t.super_sparse_degree = 10;
   return t;
 }
 
@@ -1255,6 +1354,8 @@ sssp_tuning resolve_tuning(const sssp_tuning* in) {
   if (!t.list_divisor) t.list_divisor = d.list_divisor;
   if (!t.sample_cap) t.sample_cap = d.sample_cap;
   if (!t.probe_cap) t.probe_cap = d.probe_cap;
+  if (!t.local_budget) t.local_budget = d.local_budget;
+  if (!t.super_sparse_degree) t.super_sparse_degree = d.super_sparse_degree;
   return t;
 }
 
@@ -1384,6 +1485,7 @@ sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uin
   KArgs& a = L.a;
   std::memset(&a, 0, sizeof(a));
   a.n = g->n;
+  a.m = (uint64_t)g->m;
   a.nwords = geo.nwords;
   a.off = (const int64_t*)g->off.p;
   a.edges = (const ull*)g->edges.p;
@@ -1422,6 +1524,9 @@ sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uin
   a.probe_cap = tu.probe_cap;
   a.filter = tu.no_filter ? 0u : 1u;
   a.snapshot = (p.flags & SSSP_SOLVE_SNAPSHOT_KEYS) ? 1u : 0u;
+  // Local expansion reads current keys, so snapshot-key runs go without it.
+  a.local_budget = (a.snapshot || tu.local_budget == 0xFFFFFFFFu) ? 0u : tu.local_budget;
+  a.super_sparse = tu.super_sparse_degree;
   return SSSP_OK;
 }
 
@@ -1460,6 +1565,7 @@ sssp_status collect_stats(sssp_graph* g, const Launch& L, hipStream_t st, sssp_s
     stats->queue_dense += tc.st_qdense;
     stats->queue_list += tc.st_qlist;
     stats->list_appends += tc.st_appends;
+    stats->local_vertices += tc.st_local;
     if (t == 0) {
       for (int k = 0; k < 4; ++k) stats->phase_ms[k] = (double)tc.phase_ticks[k] / (double)g->tick_khz;
       stats->relax_wg_ms[0] = (double)tc.relax_busy_max / (double)g->tick_khz;

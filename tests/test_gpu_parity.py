@@ -97,10 +97,16 @@ def test_theta_min_exact_loop_counts(sp):
         assert st["steps"] == oracle.distinct_finite(exp)
         assert st["extracted"] == int((exp != INF).sum())
         assert st["edges_relaxed"] == oracle.reachable_arcs(g.offsets, exp)
+        assert st["local_vertices"] == 0  # nothing lands at or below theta = min when w >= 1
+
+
+NO_LOCAL = dict(local_budget=0xFFFFFFFF)  # Alg. 1 as printed: every relaxed vertex went through Extract
 
 
 def test_extraction_bound_lemma_5_1(sp):
     # Positive weights: vertex v is extracted at most max(1, hop[v]) times.
+    # Without local expansion every reachable vertex is extracted; with it,
+    # vertices relaxed inside a step need no extraction, and the bound holds.
     g = graphgen.road(120, 120, seed=8)
     s = int(graphgen.pick_sources(g.n, 1, 9, graphgen.largest_component(g))[0])
     exp = ref(g, s)
@@ -109,12 +115,14 @@ def test_extraction_bound_lemma_5_1(sp):
     bound[hop < 0] = 0
     G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
     for rule, kw in [("rho", {"rho": 512}), ("delta", {"delta": 4000}), ("bf", {})]:
-        dist, st = sp.solve(G, [s], rule=rule, extract_counts=True, **kw)
-        assert_same(sp.to_numpy_u64(dist)[0], exp, rule)
-        cnt = st["extract_counts"].cpu().numpy()[0]
-        assert np.all(cnt <= bound), (rule, int(np.argmax(cnt - bound)))
-        assert np.all(cnt[hop >= 0] >= 1)
-        assert int(cnt.sum()) == st["extracted"]
+        for tun in (NO_LOCAL, None):
+            dist, st = sp.solve(G, [s], rule=rule, extract_counts=True, tuning=tun, **kw)
+            assert_same(sp.to_numpy_u64(dist)[0], exp, rule)
+            cnt = st["extract_counts"].cpu().numpy()[0]
+            assert np.all(cnt <= bound), (rule, tun, int(np.argmax(cnt - bound)))
+            if tun is NO_LOCAL:
+                assert np.all(cnt[hop >= 0] >= 1)
+            assert int(cnt.sum()) == st["extracted"]
     G.close()
 
 
@@ -183,7 +191,9 @@ def test_tuning_variants_do_not_change_distances(sp):
     G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
     variants = [dict(hub_degree=1, chunk_edges=64), dict(hub_degree=64, chunk_edges=64),
                 dict(list_divisor=0xFFFFFFFF), dict(list_divisor=1), dict(no_filter=1), dict(blocks_per_cu=1),
-                dict(sample_cap=16, probe_cap=16), dict(hub_degree=1 << 20)]
+                dict(sample_cap=16, probe_cap=16), dict(hub_degree=1 << 20), dict(local_budget=0xFFFFFFFF),
+                dict(local_budget=1), dict(local_budget=16, super_sparse_degree=1 << 20),
+                dict(local_budget=1 << 20, super_sparse_degree=1 << 20, list_divisor=1)]
     for tv in variants:
         for rule, kw in [("rho", {"rho": 2048}), ("bf", {})]:
             dist, _ = sp.solve(G, [s], rule=rule, tuning=tv, **kw)
@@ -195,6 +205,28 @@ def test_tuning_variants_do_not_change_distances(sp):
         dist, st = sp.solve(G, [s], rule=rule, extract_counts=True, **kw)
         assert_same(sp.to_numpy_u64(dist)[0], exp, f"keep order {rule}")
         assert int(st["extract_counts"].sum()) == st["extracted"]
+    G.close()
+
+
+def test_local_expansion_on_road_graphs(sp):
+    """Local expansion (Sec. 6, large neighbour sets) leaves every distance
+    as it is and, on a high-diameter graph, needs far fewer steps."""
+    g = graphgen.road(120, 120, seed=23)
+    s = 777
+    exp = ref(g, s)
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights, reorder=False)
+    for rule, kw in [("delta", {"delta": 2000}), ("delta", {"delta": 200000}), ("bf", {}), ("rho", {"rho": 64})]:
+        steps = {}
+        for name, tun in [("off", dict(local_budget=0xFFFFFFFF)), ("on", None), ("small", dict(local_budget=8)),
+                          ("all", dict(super_sparse_degree=1 << 20, local_budget=1 << 16))]:
+            dist, st = sp.solve(G, [s], rule=rule, tuning=tun, **kw)
+            assert_same(sp.to_numpy_u64(dist)[0], exp, f"{rule} {kw} local {name}")
+            steps[name] = st["steps"]
+            if name == "off":
+                assert st["local_vertices"] == 0
+            if name == "all":
+                assert st["local_vertices"] > 0
+        assert steps["all"] < steps["off"], (rule, kw, steps)
     G.close()
 
 
@@ -285,10 +317,14 @@ def test_step_limit_and_bad_params(sp):
     g = graphgen.from_arcs(50, np.arange(49), np.arange(1, 50), np.ones(49))
     G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
     with pytest.raises(sp.SSSPError) as ei:
-        sp.solve(G, [0], rule="bf", max_steps=5)
+        sp.solve(G, [0], rule="bf", max_steps=5, tuning=NO_LOCAL)
     assert ei.value.status == 6
-    dist, st = sp.solve(G, [0], rule="bf", max_steps=50)
+    dist, st = sp.solve(G, [0], rule="bf", max_steps=50, tuning=NO_LOCAL)
     assert st["steps"] == 50  # 49 steps settle the path, one more empties Q
+    # Local expansion walks the whole path within the first step.
+    dist, st = sp.solve(G, [0], rule="bf", max_steps=5)
+    assert st["steps"] <= 2 and st["local_vertices"] >= 49
+    assert sp.to_numpy_u64(dist)[0].tolist() == list(range(50))
     for bad in (dict(rule="rho", rho=0), dict(rule="delta", delta=0)):
         with pytest.raises(sp.SSSPError) as ei:
             sp.solve(G, [0], **bad)
