@@ -154,7 +154,7 @@ def run_single(args, torch, sp, w):
                 f"E_r {st['edges_relaxed']}")
         fixed = {"rho": min(sweep, key=lambda r: r["ms"])["rho"] if sweep else (args.rho or 1 << 18)}
     else:
-        fixed = {"delta": args.delta}
+        fixed = {"delta": args.delta or int(w.params["delta"])}
 
     out = torch.empty((1, g.n), dtype=torch.int64, device="cuda")
     for _ in range(args.warmup):
@@ -499,7 +499,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
     ap.add_argument("--rho", type=int, default=0, help="rho for the timed solves (0 = the workload's default)")
-    ap.add_argument("--delta", type=int, default=1 << 13)
+    ap.add_argument("--delta", type=int, default=0, help="Delta for the road workload (0 = its default, 2^15)")
     ap.add_argument("--sweep", default="", metavar="LOG2_LIST",
                     help="e.g. 16,17,18,19,20,21,22: time 3 solves per rho first and use the fastest")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -236,7 +236,7 @@ def workload(name: str, **overrides) -> Workload:
         g = road(side, side, seed=seed)
         lcc = largest_component(g)
         src = pick_sources(g.n, nsrc, seed + 2, lcc)
-        return Workload(name, g, src, "delta", {"delta": 1 << 13})
+        return Workload(name, g, src, "delta", {"delta": 1 << 15})
     if name.startswith("knn"):
         per = int(name[3:])
         seed = overrides.pop("seed", 4001)

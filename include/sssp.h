@@ -82,6 +82,10 @@ typedef enum { SSSP_OFFSETS_I32 = 0, SSSP_OFFSETS_I64 = 1 } sssp_offset_width;
 #define SSSP_INPUT_HOST 0x1u   /* offsets/targets/weights are host pointers */
 #define SSSP_INPUT_DEVICE 0x2u /* offsets/targets/weights are device pointers */
 #define SSSP_TRUST_INPUT 0x4u  /* skip CSR validation (caller guarantees it) */
+#define SSSP_UNDIRECTED 0x10u  /* the caller asserts that every arc (u, v, w) has its reverse
+                                  (v, u, w), as in an undirected graph; checked on the device with
+                                  64-bit multiset checksums unless SSSP_TRUST_INPUT. Enables
+                                  bidirectional relaxation (sssp_tuning.pull). */
 #define SSSP_KEEP_ORDER 0x8u   /* keep the caller's vertex numbering internally (by default the
                                   library renumbers vertices by decreasing out-degree for cache
                                   locality; results are always in the caller's ids) */
@@ -111,8 +115,12 @@ typedef struct {
   uint32_t super_sparse_degree; /* steps on the explicit list whose previous step relaxed fewer
                              arcs than this per vertex count as super-sparse (default 10;
                              the first step compares the graph's average out-degree) */
-  uint32_t reserved0;
-  uint32_t reserved1;
+  uint32_t pull;          /* bidirectional relaxation (Sec. 6): before pushing from u, lower
+                             u's key with its neighbours' keys. Needs a graph created with
+                             SSSP_UNDIRECTED. 0 = library default (off), 1 = on
+                             (INVALID_ARGUMENT on other graphs), 0xFFFFFFFF = off; always off
+                             with SSSP_SOLVE_SNAPSHOT_KEYS */
+  uint32_t reserved;
 } sssp_tuning;
 
 /* One record per step, written when params.trace is set. */

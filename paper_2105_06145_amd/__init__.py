@@ -101,13 +101,16 @@ class Graph:
 
     @classmethod
     def from_csr(cls, offsets, targets, weights, validate: bool = True, reorder: bool = True,
-                 stream=None) -> "Graph":
+                 undirected: bool = False, stream=None) -> "Graph":
         """offsets (n+1, int32 or int64), targets (m, int32), weights (m,
         uint32): numpy arrays (host) or torch CUDA tensors (device). The
         library copies them into its own layout (renumbered by decreasing
-        degree unless reorder=False; results always use the caller's ids)."""
+        degree unless reorder=False; results always use the caller's ids).
+        undirected=True asserts symmetric arcs (checked unless validate=False)
+        and allows bidirectional relaxation (tuning pull=1)."""
         torch = _torch()
-        flags = (0 if validate else N.SSSP_TRUST_INPUT) | (0 if reorder else N.SSSP_KEEP_ORDER)
+        flags = (0 if validate else N.SSSP_TRUST_INPUT) | (0 if reorder else N.SSSP_KEEP_ORDER) | \
+            (N.SSSP_UNDIRECTED if undirected else 0)
         if isinstance(offsets, torch.Tensor):
             if not (offsets.is_cuda and targets.is_cuda and weights.is_cuda):
                 raise ValueError("torch inputs must be CUDA tensors")

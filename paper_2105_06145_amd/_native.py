@@ -43,6 +43,7 @@ SSSP_INPUT_HOST = 0x1
 SSSP_INPUT_DEVICE = 0x2
 SSSP_TRUST_INPUT = 0x4
 SSSP_KEEP_ORDER = 0x8
+SSSP_UNDIRECTED = 0x10
 SSSP_SOLVE_SNAPSHOT_KEYS = 0x1
 SSSP_SERVE_HASH = 0x1
 
@@ -53,7 +54,7 @@ class sssp_tuning(ctypes.Structure):
                 ("sample_cap", ctypes.c_uint32), ("probe_cap", ctypes.c_uint32),
                 ("no_filter", ctypes.c_uint32), ("teams", ctypes.c_uint32),
                 ("local_budget", ctypes.c_uint32), ("super_sparse_degree", ctypes.c_uint32),
-                ("reserved0", ctypes.c_uint32), ("reserved1", ctypes.c_uint32)]
+                ("pull", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class sssp_step_record(ctypes.Structure):

@@ -61,6 +61,34 @@ __global__ void validate_kernel(const int64_t* off, const int32_t* tgt, ull n, u
   }
 }
 
+// Multiset checksums of the arcs (u, v, w) and of their reverses (v, u, w):
+// equal for a symmetric graph. Each term is the SplitMix64 finaliser of a
+// mix of the three fields; sums are modulo 2^64.
+__device__ __forceinline__ ull arc_mix(ull a, ull b, ull w) {
+  ull z = a * 0x9e3779b97f4a7c15ull ^ (b + 0x632be59bd9b4e019ull) * 0xd1b54a32d192ed03ull ^ w;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__global__ void symmetry_hash_kernel(const int64_t* off, const ull* edges, ull n, ull* sums) {
+  ull fwd = 0, rev = 0;
+  for (ull u = (ull)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (ull)gridDim.x * blockDim.x)
+    for (int64_t e = off[u]; e < off[u + 1]; ++e) {
+      const ull v = edges[e] & 0xffffffffull, w = edges[e] >> 32;
+      fwd += arc_mix(u, v, w);
+      rev += arc_mix(v, u, w);
+    }
+  for (int o = 32; o > 0; o >>= 1) {
+    fwd += __shfl_xor(fwd, o);
+    rev += __shfl_xor(rev, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&sums[0], fwd);
+    atomicAdd(&sums[1], rev);
+  }
+}
+
 // Sort keys for the relabelling: smaller key = larger out-degree.
 __global__ void degree_keys_kernel(const int64_t* off, ull n, uint32_t* keys, int32_t* ids) {
   for (ull v = (ull)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (ull)gridDim.x * blockDim.x) {
@@ -207,7 +235,7 @@ sssp_status sssp_graph_create(int64_t n, int64_t m, sssp_offset_width ow, const 
     return fail(SSSP_ERR_INVALID_ARGUMENT, "int32 offsets need m < 2^31");
   const bool host = (flags & SSSP_INPUT_HOST) != 0, device = (flags & SSSP_INPUT_DEVICE) != 0;
   if (host == device) return fail(SSSP_ERR_INVALID_ARGUMENT, "exactly one of SSSP_INPUT_HOST/DEVICE");
-  if (flags & ~(SSSP_INPUT_HOST | SSSP_INPUT_DEVICE | SSSP_TRUST_INPUT | SSSP_KEEP_ORDER))
+  if (flags & ~(SSSP_INPUT_HOST | SSSP_INPUT_DEVICE | SSSP_TRUST_INPUT | SSSP_KEEP_ORDER | SSSP_UNDIRECTED))
     return fail(SSSP_ERR_INVALID_ARGUMENT, "unknown flag bits");
   if (!offsets || (m > 0 && (!targets || !weights))) return fail(SSSP_ERR_INVALID_ARGUMENT, "NULL array");
   const bool trust = (flags & SSSP_TRUST_INPUT) != 0;
@@ -293,6 +321,23 @@ sssp_status sssp_graph_create(int64_t n, int64_t m, sssp_offset_width ow, const 
       pack_edges_kernel<<<2048, 256, 0, st>>>(tsrc, wsrc, (ull*)g->edges.p, (ull)m);
       if ((e = hipGetLastError()) != hipSuccess) break;
     }
+    if ((flags & SSSP_UNDIRECTED) && !trust && m > 0) {
+      if ((e = flag.alloc(16, st)) != hipSuccess) break;
+      if ((e = hipMemsetAsync(flag.p, 0, 16, st)) != hipSuccess) break;
+      symmetry_hash_kernel<<<1024, 256, 0, st>>>((const int64_t*)g->off.p, (const ull*)g->edges.p, (ull)n,
+                                                 (ull*)flag.p);
+      ull sums[2] = {0, 1};
+      if ((e = hipGetLastError()) == hipSuccess &&
+          (e = hipMemcpyAsync(sums, flag.p, 16, hipMemcpyDeviceToHost, st)) == hipSuccess)
+        e = hipStreamSynchronize(st);
+      if (e != hipSuccess) break;
+      if (sums[0] != sums[1]) {
+        rs = SSSP_ERR_INVALID_GRAPH;
+        msg = "SSSP_UNDIRECTED: the arcs are not symmetric (some (u, v, w) lacks its reverse (v, u, w))";
+        break;
+      }
+    }
+    g->undirected = (flags & SSSP_UNDIRECTED) != 0;
     e = hipStreamSynchronize(st);
   } while (false);
   t32.release(st);

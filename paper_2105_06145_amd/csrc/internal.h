@@ -68,6 +68,7 @@ struct sssp_graph {
   sssp_impl::DevBuf edges;  // uint64[m]: (weight << 32) | internal target
   sssp_impl::DevBuf perm, inv;
   bool relabelled = false;
+  bool undirected = false;  // every arc (u, v, w) has its reverse (v, u, w)
   bool serving = false;  // a persistent server owns the workspace
   // Workspace.
   bool ws_ready = false;

@@ -184,6 +184,7 @@ struct KArgs {
   uint32_t filter;
   uint32_t snapshot;  // relax with the keys at extraction
   uint32_t local_budget;  // vertices a workgroup may relax by local expansion per step (0: off)
+  uint32_t pull;          // bidirectional relaxation (undirected graphs)
   uint32_t super_sparse;  // local expansion in list steps below this average out-degree
   // Serving mode: requests come from a ring in host memory instead of srcs.
   uint32_t serve;
@@ -204,6 +205,7 @@ constexpr ull SERVE_EXIT = ~0ull;
 struct Shared {
   ull beg[WG];
   ull du[WG];
+  ull pulled[WG];  // bidirectional relaxation: best key each tile vertex can take from its neighbours
   uint32_t pre[WG + 1];
   uint32_t hist[WG];
   uint32_t wsum[WAVES];
@@ -833,7 +835,39 @@ __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* 
   sh.pre[tid] = excl;
   sh.beg[tid] = rb;
   sh.du[tid] = du;
+  sh.pulled[tid] = du;
   __syncthreads();
+  if (a.pull) {
+    // Bidirectional relaxation (Sec. 6): first lower each vertex's key with
+    // its neighbours' keys (the arcs are symmetric), then push with it.
+    for (uint32_t e0 = 0; e0 < total; e0 += WG * UNROLL) {
+#pragma unroll
+      for (int k = 0; k < UNROLL; ++k) {
+        const uint32_t e = e0 + k * WG + tid;
+        if (e < total) {
+          int lo = 0;
+#pragma unroll
+          for (int step = WG / 2; step > 0; step >>= 1)
+            if (sh.pre[lo + step] <= e) lo += step;
+          const ull arc = a.edges[sh.beg[lo] + (e - sh.pre[lo])];
+          const ull dv = ld_plain(&dist[(uint32_t)arc]);
+          if (dv != INF) {
+            const ull cand = dv + (arc >> 32);
+            if (cand < sh.pulled[lo]) atomicMin(&sh.pulled[lo], cand);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (u >= 0 && sh.pulled[tid] < du) {
+      // u's arcs are all pushed below with the lower key, so u need not
+      // return to Q (a WriteMin of another workgroup on u still marks it).
+      atom_min(&dist[u], sh.pulled[tid]);
+      sh.du[tid] = sh.pulled[tid];
+      ++acc.succ;
+    }
+    __syncthreads();
+  }
   for (uint32_t e0 = 0; e0 < total; e0 += WG * UNROLL) {
     ull ev[UNROLL], dd[UNROLL];
 #pragma unroll
@@ -873,11 +907,38 @@ __device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S,
   for (ull item = tm.rank; item < nH; item += tm.T) {
     const ull task = ld_agent(&tm.H[2 * item]);
     const int32_t u = (int32_t)(task >> 32);
-    const ull du = a.snapshot ? ld_agent(&tm.H[2 * item + 1]) : ld_agent(&dist[u]);
+    ull du = a.snapshot ? ld_agent(&tm.H[2 * item + 1]) : ld_agent(&dist[u]);
     const ull c = task & 0xffffffffull;
     const ull rb = (ull)a.off[u], re = (ull)a.off[u + 1];
     const ull beg = rb + c * CH;
     const ull end = umin(beg + CH, re);
+    if (a.pull) {
+      // Bidirectional relaxation over this chunk's neighbours. Other chunks
+      // of u may already have pushed with the older key, so a lower key
+      // also puts u back in Q.
+      ull best = du;
+      for (ull e = beg + tid; e < end; e += WG) {
+        const ull arc = a.edges[e];
+        const ull dv = ld_plain(&dist[(uint32_t)arc]);
+        if (dv != INF) best = umin(best, dv + (arc >> 32));
+      }
+      ull z0 = 0, z1 = 0, z2 = 0;
+      wg_reduce4(sh, z0, z1, z2, best);
+      if (best < du) {
+        int32_t v1[1] = {u};
+        unsigned m1 = 0;
+        if (tid == 0 && best < atom_min(&dist[u], best)) {
+          ++acc.succ;
+          acc.minnew = umin(acc.minnew, best);
+          if (mark(tm.bitmap, u)) {
+            ++acc.fresh;
+            m1 = 1;
+          }
+        }
+        if (emit) list_append(a, S, Lnext, v1, m1);
+        du = best;
+      }
+    }
     for (ull e0 = beg; e0 < end; e0 += (ull)WG * UNROLL) {
       ull ev[UNROLL], dd[UNROLL];
 #pragma unroll
@@ -1476,6 +1537,8 @@ sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uin
   if (L.nteams > L.G || L.G % L.nteams != 0)
     return fail(SSSP_ERR_INVALID_ARGUMENT, "teams must divide the grid of " + std::to_string(L.G) + " workgroups");
   L.geo = make_geometry(g, L.tu, L.G, L.nteams);
+  if (L.tu.pull == 1 && !g->undirected)
+    return fail(SSSP_ERR_INVALID_ARGUMENT, "pull = 1 needs a graph created with SSSP_UNDIRECTED");
   sssp_status ws = ensure_workspace(g, L.tu, L.geo, st);
   if (ws != SSSP_OK) return ws;
 
@@ -1527,6 +1590,8 @@ sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uin
   // Local expansion reads current keys, so snapshot-key runs go without it.
   a.local_budget = (a.snapshot || tu.local_budget == 0xFFFFFFFFu) ? 0u : tu.local_budget;
   a.super_sparse = tu.super_sparse_degree;
+  // Bidirectional relaxation reads current keys too; it needs symmetric arcs.
+  a.pull = (!a.snapshot && g->undirected && tu.pull != 0xFFFFFFFFu && tu.pull != 0) ? 1u : 0u;
   return SSSP_OK;
 }
 

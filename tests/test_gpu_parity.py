@@ -230,6 +230,36 @@ def test_local_expansion_on_road_graphs(sp):
     G.close()
 
 
+def test_bidirectional_relaxation(sp):
+    """Pull-then-push relaxation (Sec. 6) on symmetric graphs leaves every
+    distance as it is; it is refused on graphs not declared undirected, and
+    an asymmetric graph declared undirected is rejected."""
+    for g, s, rules in [(graphgen.rmat(14, 16, seed=24), None, [("rho", {"rho": 1000}), ("bf", {})]),
+                        (graphgen.road(90, 90, seed=25), 4000, [("delta", {"delta": 3000}), ("rho", {"rho": 64})])]:
+        s = int(np.argmax(g.degrees())) if s is None else s
+        exp = ref(g, s)
+        G = sp.Graph.from_csr(g.offsets, g.targets, g.weights, undirected=True)
+        for rule, kw in rules:
+            for tun in (dict(pull=1), dict(pull=1, hub_degree=16, chunk_edges=64), dict(pull=1, local_budget=64),
+                        dict(pull=0xFFFFFFFF)):
+                dist, _ = sp.solve(G, [s], rule=rule, tuning=tun, **kw)
+                assert_same(sp.to_numpy_u64(dist)[0], exp, f"{rule} {kw} {tun}")
+            dist, _ = sp.solve(G, [s, 0, 5], rule=rule, tuning=dict(pull=1, teams=8), **kw)
+            for i, src in enumerate([s, 0, 5]):
+                assert_same(sp.to_numpy_u64(dist)[i], ref(g, src), f"batched pull {rule} row {i}")
+        G.close()
+    g = graphgen.rmat(10, 8, seed=26)
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+    with pytest.raises(sp.SSSPError) as ei:
+        sp.solve(G, [0], tuning=dict(pull=1))
+    assert ei.value.status == 1
+    G.close()
+    one_way = graphgen.from_arcs(4, [0, 1, 2], [1, 2, 3], [5, 5, 5])
+    with pytest.raises(sp.SSSPError) as ei:
+        sp.Graph.from_csr(one_way.offsets, one_way.targets, one_way.weights, undirected=True)
+    assert ei.value.status == 2 and "symmetric" in str(ei.value)
+
+
 def test_seeds_and_repeats_agree(sp):
     g = graphgen.rmat(14, 16, seed=15)
     s = int(np.argmax(g.degrees()))
