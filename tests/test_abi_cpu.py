@@ -127,3 +127,34 @@ def test_null_arguments():
     assert "NULL" in N.sssp_last_error()
     assert N.sssp_graph_destroy(None) == N.SSSP_OK
     assert N.sssp_graph_info(None)[0] == N.SSSP_ERR_INVALID_ARGUMENT
+
+
+def test_serving_and_checksum_null_arguments():
+    # Every check here returns before any device call.
+    lib = N.lib()
+    p = N.sssp_default_params()
+    s = ctypes.c_void_p()
+    assert lib.sssp_server_start(None, ctypes.byref(p), None, 1, 1, 0, 0, None, None) == N.SSSP_ERR_INVALID_ARGUMENT
+    assert lib.sssp_server_start(None, ctypes.byref(p), None, 1, 1, 0, 0, None,
+                                 ctypes.byref(s)) == N.SSSP_ERR_INVALID_ARGUMENT
+    assert not s.value
+    t = ctypes.c_uint64()
+    assert lib.sssp_server_submit(None, 0, 0, ctypes.byref(t)) == N.SSSP_ERR_INVALID_ARGUMENT
+    c = ctypes.c_uint32()
+    assert lib.sssp_server_poll(None, None, None, 0, ctypes.byref(c)) == N.SSSP_ERR_INVALID_ARGUMENT
+    assert lib.sssp_server_stop(None, None) == N.SSSP_ERR_INVALID_ARGUMENT
+    assert lib.sssp_server_destroy(None) == N.SSSP_OK
+    h = ctypes.c_uint64()
+    assert lib.sssp_row_hash(None, 5, None, ctypes.byref(h)) == N.SSSP_ERR_INVALID_ARGUMENT
+    assert "NULL" in N.sssp_last_error()
+
+
+def test_graph_create_rejects_unknown_flag_bits():
+    lib = N.lib()
+    off = np.array([0, 1, 2], dtype=np.int64)
+    tgt = np.array([1, 0], dtype=np.int32)
+    w = np.array([3, 3], dtype=np.uint32)
+    h = ctypes.c_void_p()
+    ptrs = [ctypes.c_void_p(a.ctypes.data) for a in (off, tgt, w)]
+    rc = lib.sssp_graph_create(2, 2, N.SSSP_OFFSETS_I64, *ptrs, N.SSSP_INPUT_HOST | 0x100, None, ctypes.byref(h))
+    assert rc == N.SSSP_ERR_INVALID_ARGUMENT and "flag" in N.sssp_last_error()
