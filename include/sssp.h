@@ -134,6 +134,9 @@ typedef struct {
                          bit 1: an explicit list was built for the next step;
                          bit 2: theta came from sampling */
   uint32_t samples;   /* sample size when bit 2 is set */
+  uint64_t local;     /* vertices relaxed by local expansion */
+  uint64_t extract_ns; /* wall-clock time of the step's threshold and Extract phases */
+  uint64_t relax_ns;   /* wall-clock time of the step's Relax phase (with local expansion) */
 } sssp_step_record;
 
 /* sssp_params.flags */

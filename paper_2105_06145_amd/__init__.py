@@ -225,7 +225,8 @@ def solve(g: Graph, sources, rule: str = "rho", rho: int = 1 << 20, delta: int =
         for i in range(min(int(trace), int(stats["steps"]) if ns == 1 else int(trace))):
             r = raw[i]
             recs.append({"theta": int(r[0]), "q": int(r[1]), "extracted": int(r[2]), "edges": int(r[3]),
-                         "successes": int(r[4]), "flags": int(r[5]) & 0xFFFFFFFF, "samples": int(r[5]) >> 32})
+                         "successes": int(r[4]), "flags": int(r[5]) & 0xFFFFFFFF, "samples": int(r[5]) >> 32,
+                         "local": int(r[6]), "extract_ns": int(r[7]), "relax_ns": int(r[8])})
         stats["trace"] = recs
     return out, stats
 

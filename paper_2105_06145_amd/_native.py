@@ -60,7 +60,8 @@ class sssp_tuning(ctypes.Structure):
 class sssp_step_record(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_uint64), ("q", ctypes.c_uint64), ("extracted", ctypes.c_uint64),
                 ("edges", ctypes.c_uint64), ("successes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
-                ("samples", ctypes.c_uint32)]
+                ("samples", ctypes.c_uint32), ("local", ctypes.c_uint64), ("extract_ns", ctypes.c_uint64),
+                ("relax_ns", ctypes.c_uint64)]
 
 
 class sssp_params(ctypes.Structure):

@@ -184,6 +184,7 @@ struct KArgs {
   uint32_t filter;
   uint32_t snapshot;  // relax with the keys at extraction
   uint32_t local_budget;  // vertices a workgroup may relax by local expansion per step (0: off)
+  uint32_t ns_per_tick;   // wall-clock counter period
   uint32_t pull;          // bidirectional relaxation (undirected graphs)
   uint32_t super_sparse;  // local expansion in list steps below this average out-degree
   // Serving mode: requests come from a ring in host memory instead of srcs.
@@ -213,6 +214,7 @@ struct Shared {
   ull bcast[4];
   int32_t lq[2][LQ];  // local expansion: this round's vertices and the next round's
   uint32_t lqn[2];
+  uint32_t fcnt;  // F entries reserved by this workgroup in a bitmap step
   int last;
   int abort;
 };
@@ -258,6 +260,10 @@ template <class P>
 __device__ __forceinline__ ull ld_agent(P p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Streaming load for the arc array: each arc is read once per relaxation
+// pass, so it is marked non-temporal and does not push the keys of
+// frequently relaxed targets out of L2.
+__device__ __forceinline__ ull ld_stream(const ull* p) { return __builtin_nontemporal_load(p); }
 template <class P>
 __device__ __forceinline__ int32_t ld_agent_i32(P p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -736,6 +742,76 @@ __device__ __noinline__ ExtractOut phase_extract_dense(const KArgs& a, const ull
   return o;
 }
 
+// S2, bitmap step without an explicit list to build. Each lane owns words as
+// above and walks its members on its own (no workgroup barrier), reserving F
+// slots with an LDS counter.
+__device__ __noinline__ ExtractOut phase_extract_dense_fast(const KArgs& a, const ull* dist, StepSlot* S,
+                                                            ull theta) {
+  const Team& tm = g_tm;
+  Shared& sh = g_sh;
+  const ull nw = a.nwords, T = tm.T;
+  const ull nblocks = (nw + BLOCK_WORDS - 1) / BLOCK_WORDS;
+  constexpr ull BLOCKS_PER_ROUND = WG / BLOCK_WORDS;
+  ExtractOut o{0, 0, INF};
+  if (threadIdx.x == 0) sh.fcnt = 0;
+  __syncthreads();
+  uint32_t* xc = a.xcount ? a.xcount + ld_agent(&tm.ctl->query) * (ull)a.n : nullptr;
+  for (ull r0 = tm.rank; r0 < nblocks; r0 += T * BLOCKS_PER_ROUND) {
+    const ull blk = r0 + T * (threadIdx.x / BLOCK_WORDS);
+    const ull wi = blk * BLOCK_WORDS + (threadIdx.x % BLOCK_WORDS);
+    if (blk >= nblocks || wi >= nw) continue;
+    const ull word = ld_agent(&tm.bitmap[wi]);
+    if (!word) continue;
+    const ull hubw = ld_plain(&a.hubmask[wi]);
+    ull rest = word, clear = 0;
+    while (rest) {
+      int32_t v[BATCH];
+      ull d[BATCH];
+#pragma unroll
+      for (int k = 0; k < BATCH; ++k) {
+        v[k] = -1;
+        if (rest) {
+          const int bit = __ffsll((long long)rest) - 1;
+          rest &= rest - 1;
+          v[k] = (int32_t)(wi * 64 + bit);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < BATCH; ++k) d[k] = v[k] >= 0 ? ld_agent(&dist[v[k]]) : INF;
+#pragma unroll
+      for (int k = 0; k < BATCH; ++k) {
+        if (v[k] < 0) continue;
+        const ull bit = 1ull << (v[k] & 63);
+        bool ext = d[k] <= theta;
+        if (ext) {
+          if ((hubw & bit) != 0) {
+            push_hub(a, tm.H, S, v[k], d[k]);
+          } else {
+            const uint32_t slot = atomicAdd(&sh.fcnt, 1u);
+            if (slot < a.segcap) {
+              tm.Fb[slot] = v[k];
+              if (a.snapshot) tm.FDb[slot] = d[k];
+            } else {
+              ext = false;  // no room: stays queued
+            }
+          }
+        }
+        if (ext) {
+          clear |= bit;
+          ++o.x;
+          if (xc) xc[a.perm ? a.perm[v[k]] : v[k]] += 1u;
+        } else {
+          o.minkept = umin(o.minkept, d[k]);
+        }
+      }
+    }
+    if (clear) tm.bitmap[wi] = word & ~clear;
+  }
+  __syncthreads();
+  o.fcnt = (uint32_t)umin((ull)sh.fcnt, a.segcap);
+  return o;
+}
+
 // S2, list step: this workgroup's contiguous slice of the explicit list.
 __device__ __noinline__ ExtractOut phase_extract_list(const KArgs& a, const ull* dist, StepSlot* S,
                                                       const int32_t* Lcur, int32_t* Lnext, ull q, ull theta,
@@ -880,7 +956,7 @@ __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* 
 #pragma unroll
         for (int step = WG / 2; step > 0; step >>= 1)
           if (sh.pre[lo + step] <= e) lo += step;
-        ev[k] = a.edges[sh.beg[lo] + (e - sh.pre[lo])];
+        ev[k] = ld_stream(&a.edges[sh.beg[lo] + (e - sh.pre[lo])]);
         dd[k] = sh.du[lo];
       }
     }
@@ -944,7 +1020,7 @@ __device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S,
 #pragma unroll
       for (int k = 0; k < UNROLL; ++k) {
         const ull e = e0 + (ull)k * WG + tid;
-        ev[k] = e < end ? a.edges[e] : INF;
+        ev[k] = e < end ? ld_stream(&a.edges[e]) : INF;
         dd[k] = du;
       }
       relax_batch(a, tm, dist, S, Lnext, emit, acc, lx, ev, dd);
@@ -1021,7 +1097,7 @@ __device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S,
 // workgroups, publish the step totals, clear the slot two steps ahead, update
 // stats and the trace.
 __device__ __noinline__ void step_bookkeeping(const KArgs& a, StepSlot* S, ull t, ull q, ull theta,
-                                              unsigned flags) {
+                                              unsigned flags, ull extract_ticks, ull relax_start) {
   const Team& tm = g_tm;
   Shared& sh = g_sh;
   const unsigned tid = threadIdx.x;
@@ -1077,6 +1153,9 @@ __device__ __noinline__ void step_bookkeeping(const KArgs& a, StepSlot* S, ull t
       r.successes = s;
       r.flags = flags;
       r.samples = (flags & 4u) ? (uint32_t)ld_agent(&S->nsamples) : 0u;
+      r.local = lv;
+      r.extract_ns = extract_ticks * a.ns_per_tick;
+      r.relax_ns = (ull)(wall_clock64() - (long long)relax_start) * a.ns_per_tick;
       a.trace[t] = r;
     }
   }
@@ -1275,6 +1354,7 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
     bool list_valid = true;
 
     for (ull t = 0;; ++t) {
+      const long long t_step = wall_clock64();
       if (q == 0) break;
       if (a.max_steps && t >= a.max_steps) {
         if (tm.rank == 0 && tid == 0) tm.ctl->status |= ST_STEP_LIMIT;
@@ -1301,7 +1381,9 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
         ull prod;
         theta = __builtin_mul_overflow(i, (ull)a.delta, &prod) ? INF : prod;
       } else {
+        // The first two bitmap steps use rho / 10 (Sec. 6).
         const ull rho_eff = (dense && dense_steps < 2) ? ((a.rho / 10) > 0 ? a.rho / 10 : 1) : a.rho;
+        if (dense) ++dense_steps;
         if (q > rho_eff) {
           sampled = true;
           const ull probes = rho_probes(q, rho_eff, n, dense, a.sample_cap, a.probe_cap);
@@ -1324,10 +1406,12 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
       }
 
       // ---- S2: Extract(theta) over this workgroup's slice ----
-      const ExtractOut ex = dense ? phase_extract_dense(a, dist, S, Lnext, theta, emit)
-                                  : phase_extract_list(a, dist, S, Lcur, Lnext, q, theta, emit);
+      const ExtractOut ex = !dense  ? phase_extract_list(a, dist, S, Lcur, Lnext, q, theta, emit)
+                            : emit ? phase_extract_dense(a, dist, S, Lnext, theta, emit)
+                                   : phase_extract_dense_fast(a, dist, S, theta);
       if (!team_sync(a, sh, tm, NoSerial{})) return;
       ph2 += lap();
+      const long long t_relax = wall_clock64();
 
       // ---- S3/S4: Relax + Update ----
       // Local expansion in super-sparse steps: list steps whose previous
@@ -1335,7 +1419,9 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
       const bool local = a.local_budget && !dense && prev_e < (ull)a.super_sparse * umin(prev_x, INF / 64);
       phase_relax(a, dist, S, Lnext, emit, ex, local, theta);
       const unsigned flags = (dense ? 1u : 0u) | (emit ? 2u : 0u) | (sampled ? 4u : 0u);
-      auto bookkeeping = [&]() { step_bookkeeping(a, S, t, q, theta, flags); };
+      auto bookkeeping = [&]() {
+        step_bookkeeping(a, S, t, q, theta, flags, (ull)(t_relax - t_step), (ull)t_relax);
+      };
       if (!team_sync(a, sh, tm, bookkeeping)) return;
       ph3 += lap();
 
@@ -1345,7 +1431,6 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
       prev_x = ld_agent(&S->x_total) + ld_agent(&S->local_v);
       prev_e = ld_agent(&S->edges);
       list_valid = emit && ld_agent(&S->list_next) <= a.lcap;
-      if (dense) ++dense_steps;
     }
     // Distances back in the caller's vertex ids, and the row checksum.
     ull h = 0;
@@ -1576,6 +1661,7 @@ sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uin
   a.list_threshold = tu.list_divisor == 0xFFFFFFFFu ? 0 : std::max<uint64_t>(1, (uint64_t)g->n / tu.list_divisor);
   a.list_threshold = std::min<uint64_t>(a.list_threshold, geo.lcap);
   a.tlimit = g->tick_khz * 1000ull * 20ull;  // 20 s per barrier wait
+  a.ns_per_tick = (uint32_t)std::max<uint64_t>(1, 1000000ull / g->tick_khz);
   a.segcap = geo.segcap;
   a.hcap = geo.hcap;
   a.lcap = geo.lcap;
