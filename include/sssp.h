@@ -73,7 +73,15 @@ typedef enum {
   SSSP_RULE_BF = 2,
   /* theta = the minimum key in Q (Table 2, Dijkstra row). Sequential by
    * nature; provided so tests can pin exact step counts. */
-  SSSP_RULE_MIN = 3
+  SSSP_RULE_MIN = 3,
+  /* rho-stepping with the exact rho-th smallest key in Q (Table 2, rho row)
+   * instead of a sampled estimate: a radix selection over every queued key,
+   * 8 bits per pass below the highest bit where the queue's minimum and
+   * maximum keys differ. Each step then extracts at least min(rho, q)
+   * vertices, exactly rho when keys are distinct. Costs one pass over the
+   * queue per 8 bits (plus one for the bounds) where sampling costs one
+   * small sample. rho >= 1. */
+  SSSP_RULE_RHO_EXACT = 4
 } sssp_rule;
 
 typedef enum { SSSP_OFFSETS_I32 = 0, SSSP_OFFSETS_I64 = 1 } sssp_offset_width;
@@ -132,7 +140,8 @@ typedef struct {
   uint64_t successes; /* WriteMin calls that lowered a distance */
   uint32_t flags;     /* bit 0: Extract scanned the bitmap (else the list);
                          bit 1: an explicit list was built for the next step;
-                         bit 2: theta came from sampling */
+                         bit 2: theta came from sampling;
+                         bit 3: theta came from the exact selection */
   uint32_t samples;   /* sample size when bit 2 is set */
   uint64_t local;     /* vertices relaxed by local expansion */
   uint64_t extract_ns; /* wall-clock time of the step's threshold and Extract phases */

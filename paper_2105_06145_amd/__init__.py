@@ -19,7 +19,8 @@ import ctypes
 import numpy as np
 
 from . import _native as N
-from ._native import (SSSP_RULE_BF, SSSP_RULE_DELTA_STAR, SSSP_RULE_MIN, SSSP_RULE_RHO, sssp_abi_version,
+from ._native import (SSSP_RULE_BF, SSSP_RULE_DELTA_STAR, SSSP_RULE_MIN, SSSP_RULE_RHO, SSSP_RULE_RHO_EXACT,
+                      sssp_abi_version,
                       sssp_default_params, sssp_graph_create, sssp_graph_destroy, sssp_graph_info,
                       sssp_last_error, sssp_params, sssp_row_hash, sssp_server_destroy, sssp_server_poll,
                       sssp_server_start, sssp_server_stop, sssp_server_submit, sssp_solve, sssp_stats,
@@ -32,7 +33,8 @@ __all__ = ["Graph", "solve", "Server", "row_hash", "SSSPError", "to_numpy_u64", 
            "sssp_server_stop", "sssp_server_destroy"]
 
 INF = 0xFFFFFFFFFFFFFFFF
-RULES = {"rho": SSSP_RULE_RHO, "delta": SSSP_RULE_DELTA_STAR, "delta_star": SSSP_RULE_DELTA_STAR,
+RULES = {"rho": SSSP_RULE_RHO, "rho_exact": SSSP_RULE_RHO_EXACT, "delta": SSSP_RULE_DELTA_STAR,
+         "delta_star": SSSP_RULE_DELTA_STAR,
          "bf": SSSP_RULE_BF, "min": SSSP_RULE_MIN}
 
 

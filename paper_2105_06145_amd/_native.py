@@ -35,6 +35,7 @@ SSSP_RULE_RHO = 0
 SSSP_RULE_DELTA_STAR = 1
 SSSP_RULE_BF = 2
 SSSP_RULE_MIN = 3
+SSSP_RULE_RHO_EXACT = 4
 
 SSSP_OFFSETS_I32 = 0
 SSSP_OFFSETS_I64 = 1

@@ -112,6 +112,10 @@ struct TeamCtl {
   // Serving: the current request and the one still to be published.
   ull src, out_row;
   ull hash_acc;  // row checksum, summed over the team's workgroups
+  // Exact rho-th selection: key bounds, the digit histogram of the current
+  // pass, and the selection state (prefix, remaining rank, bits left).
+  ull sel_min, sel_max, sel_prefix, sel_k, sel_top;
+  ull sel_hist[256];
   ull pending;   // ticket + 1 of a finished request not yet published (0: none)
   alignas(128) StepSlot slot[3];
 };
@@ -1093,6 +1097,100 @@ __device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S,
   }
 }
 
+// One pass of the exact rho-th selection over this workgroup's share of Q
+// (the same ownership as Extract). With `bounds`: the minimum and maximum
+// key. Otherwise: the histogram of the digit (key >> shift) & mask over the
+// keys whose bits from `top` up equal those of `prefix`, added to the team's
+// histogram.
+__device__ __noinline__ void phase_select(const KArgs& a, const ull* dist, const int32_t* Lcur, ull q, bool dense,
+                                          bool bounds, int top, int shift, ull mask, ull prefix) {
+  const Team& tm = g_tm;
+  Shared& sh = g_sh;
+  const unsigned tid = threadIdx.x;
+  TeamCtl* tc = tm.ctl;
+  sh.hist[tid] = 0;
+  __syncthreads();
+  ull mn = INF, negmx = INF;
+  auto visit = [&](ull d) {
+    if (bounds) {
+      mn = umin(mn, d);
+      negmx = umin(negmx, ~d);
+    } else if (top >= 64 || (d >> top) == (prefix >> top)) {
+      atomicAdd(&sh.hist[(d >> shift) & mask], 1u);
+    }
+  };
+  if (dense) {
+    const ull nw = a.nwords, nblocks = (nw + BLOCK_WORDS - 1) / BLOCK_WORDS;
+    constexpr ull BLOCKS_PER_ROUND = WG / BLOCK_WORDS;
+    for (ull r0 = tm.rank; r0 < nblocks; r0 += tm.T * BLOCKS_PER_ROUND) {
+      const ull blk = r0 + tm.T * (tid / BLOCK_WORDS);
+      const ull wi = blk * BLOCK_WORDS + (tid % BLOCK_WORDS);
+      if (blk >= nblocks || wi >= nw) continue;
+      ull rest = ld_agent(&tm.bitmap[wi]);
+      while (rest) {
+        int32_t v[BATCH];
+        ull d[BATCH];
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k) {
+          v[k] = -1;
+          if (rest) {
+            const int bit = __ffsll((long long)rest) - 1;
+            rest &= rest - 1;
+            v[k] = (int32_t)(wi * 64 + bit);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k) d[k] = v[k] >= 0 ? ld_agent(&dist[v[k]]) : 0;
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k)
+          if (v[k] >= 0) visit(d[k]);
+      }
+    }
+  } else {
+    const ull lo = tm.rank * q / tm.T, hi = (tm.rank + 1) * q / tm.T;
+    for (ull i = lo + tid; i < hi; i += WG) visit(ld_agent(&dist[ld_agent_i32(&Lcur[i])]));
+  }
+  if (bounds) {
+    ull z0 = 0, z1 = 0, z2 = 0;
+    wg_reduce4(sh, z0, z1, z2, mn);
+    wg_reduce4(sh, z0, z1, z2, negmx);
+    if (tid == 0) {
+      atom_min(&tc->sel_min, mn);
+      atom_min(&tc->sel_max, negmx);  // holds ~max
+    }
+  } else {
+    __syncthreads();
+    if (sh.hist[tid]) atom_add(&tc->sel_hist[tid], (ull)sh.hist[tid]);
+  }
+}
+
+// Serial steps of the exact selection (thread 0 of the last workgroup at the
+// pass's barrier). After the bounds pass: start from the bits above the
+// highest bit where min and max differ. After a digit pass: pick the digit
+// whose bin holds the remaining rank.
+__device__ __noinline__ void select_serial(TeamCtl* tc, bool after_bounds, int shift, ull rank) {
+  if (after_bounds) {
+    const ull mn = ld_agent(&tc->sel_min), mx = ~ld_agent(&tc->sel_max);
+    const int top = mn == mx ? 0 : 64 - __clzll((long long)(mn ^ mx));
+    tc->sel_top = (ull)top;
+    tc->sel_prefix = top >= 64 ? 0 : (mn >> top) << top;
+    tc->sel_k = rank;
+  } else {
+    ull k = ld_agent(&tc->sel_k), acc = 0;
+    ull digit = 0;
+    for (; digit < 256; ++digit) {
+      const ull c = ld_agent(&tc->sel_hist[digit]);
+      if (acc + c >= k) break;
+      acc += c;
+    }
+    if (digit == 256) digit = 255;  // unreachable when the rank is within the queue
+    tc->sel_prefix = ld_agent(&tc->sel_prefix) | (digit << shift);
+    tc->sel_k = k - acc;
+    tc->sel_top = (ull)shift;
+  }
+  for (int i = 0; i < 256; ++i) tc->sel_hist[i] = 0;
+}
+
 // Serial section of the step's last barrier: sum the partials of the team's
 // workgroups, publish the step totals, clear the slot two steps ahead, update
 // stats and the trace.
@@ -1121,6 +1219,10 @@ __device__ __noinline__ void step_bookkeeping(const KArgs& a, StepSlot* S, ull t
   if (tid < 16) {
     ull* z = reinterpret_cast<ull*>(&tc->slot[(t + 2) % 3]);
     z[tid] = 0ull;
+  }
+  if (tid == 0) {
+    tc->sel_min = INF;  // for the next step's exact selection
+    tc->sel_max = INF;
   }
   if (tid == 0) {
     S->x_total = x;
@@ -1335,7 +1437,10 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
     {
       auto seed_source = [&]() {
         if (tid < 48) reinterpret_cast<ull*>(&tm.ctl->slot[0])[tid] = 0ull;
+        tm.ctl->sel_hist[tid] = 0;
         if (tid == 0) {
+          tm.ctl->sel_min = INF;
+          tm.ctl->sel_max = INF;
           const int32_t src = a.serve ? (int32_t)tm.ctl->src : a.srcs[qi];
           const int32_t s = a.inv ? a.inv[src] : src;
           dist[s] = 0;
@@ -1368,7 +1473,7 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
 
       // ---- S1: ExtDist ----
       ull theta = INF;
-      bool sampled = false;
+      bool sampled = false, exact = false;
       if (a.rule == SSSP_RULE_BF) {
         theta = INF;
       } else if (a.rule == SSSP_RULE_MIN) {
@@ -1380,6 +1485,29 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
         idelta = i;
         ull prod;
         theta = __builtin_mul_overflow(i, (ull)a.delta, &prod) ? INF : prod;
+      } else if (a.rule == SSSP_RULE_RHO_EXACT) {
+        if (q > a.rho) {
+          // Exact rho-th smallest key: a bounds pass, then 8-bit digit passes.
+          exact = true;
+          phase_select(a, dist, Lcur, q, dense, true, 64, 0, 0, 0);
+          auto start = [&]() {
+            if (tid == 0) select_serial(tm.ctl, true, 0, a.rho);
+          };
+          if (!team_sync(a, sh, tm, start)) return;
+          int top = (int)ld_agent(&tm.ctl->sel_top);
+          while (top > 0) {
+            const int width = top < 8 ? top : 8;
+            const int shift = top - width;
+            phase_select(a, dist, Lcur, q, dense, false, top, shift, (1ull << width) - 1, ld_agent(&tm.ctl->sel_prefix));
+            auto pick = [&]() {
+              if (tid == 0) select_serial(tm.ctl, false, shift, 0);
+            };
+            if (!team_sync(a, sh, tm, pick)) return;
+            top = shift;
+          }
+          theta = ld_agent(&tm.ctl->sel_prefix);
+          ph1 += lap();
+        }
       } else {
         // The first two bitmap steps use rho / 10 (Sec. 6).
         const ull rho_eff = (dense && dense_steps < 2) ? ((a.rho / 10) > 0 ? a.rho / 10 : 1) : a.rho;
@@ -1418,7 +1546,7 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
       // step relaxed fewer than super_sparse arcs per vertex on average.
       const bool local = a.local_budget && !dense && prev_e < (ull)a.super_sparse * umin(prev_x, INF / 64);
       phase_relax(a, dist, S, Lnext, emit, ex, local, theta);
-      const unsigned flags = (dense ? 1u : 0u) | (emit ? 2u : 0u) | (sampled ? 4u : 0u);
+      const unsigned flags = (dense ? 1u : 0u) | (emit ? 2u : 0u) | (sampled ? 4u : 0u) | (exact ? 8u : 0u);
       auto bookkeeping = [&]() {
         step_bookkeeping(a, S, t, q, theta, flags, (ull)(t_relax - t_step), (ull)t_relax);
       };
@@ -1599,9 +1727,10 @@ sssp_status check_params(const sssp_params* params, sssp_params& p, sssp_tuning&
   } else {
     sssp_default_params(&p);
   }
-  if (p.rule > SSSP_RULE_MIN) return fail(SSSP_ERR_INVALID_ARGUMENT, "unknown rule");
+  if (p.rule > SSSP_RULE_RHO_EXACT) return fail(SSSP_ERR_INVALID_ARGUMENT, "unknown rule");
   if (p.flags & ~SSSP_SOLVE_SNAPSHOT_KEYS) return fail(SSSP_ERR_INVALID_ARGUMENT, "unknown flags");
-  if (p.rule == SSSP_RULE_RHO && p.rho == 0) return fail(SSSP_ERR_INVALID_ARGUMENT, "rho must be >= 1");
+  if ((p.rule == SSSP_RULE_RHO || p.rule == SSSP_RULE_RHO_EXACT) && p.rho == 0)
+    return fail(SSSP_ERR_INVALID_ARGUMENT, "rho must be >= 1");
   if (p.rule == SSSP_RULE_DELTA_STAR && p.delta == 0) return fail(SSSP_ERR_INVALID_ARGUMENT, "delta must be >= 1");
   if (p.trace && p.trace_capacity == 0) return fail(SSSP_ERR_INVALID_ARGUMENT, "trace needs trace_capacity > 0");
   tu = resolve_tuning(p.tuning);

@@ -46,6 +46,7 @@ def assert_same(got, exp, what=""):
 
 
 RULES = [("rho", {"rho": 1}), ("rho", {"rho": 3}), ("rho", {"rho": 64}), ("rho", {"rho": 1 << 30}),
+         ("rho_exact", {"rho": 1}), ("rho_exact", {"rho": 7}), ("rho_exact", {"rho": 100}),
          ("delta", {"delta": 1}), ("delta", {"delta": 777}), ("delta", {"delta": 1 << 40}), ("bf", {}),
          ("min", {})]
 
@@ -258,6 +259,38 @@ def test_bidirectional_relaxation(sp):
     with pytest.raises(sp.SSSPError) as ei:
         sp.Graph.from_csr(one_way.offsets, one_way.targets, one_way.weights, undirected=True)
     assert ei.value.status == 2 and "symmetric" in str(ei.value)
+
+
+def test_exact_rho_selection_on_a_star(sp):
+    """With the exact rho-th key (NEXT-4 rule), a star whose leaf weights are
+    a permutation of 1..N is settled rho leaves per step: the trace shows
+    exactly rho extractions per step until at most rho leaves remain, and
+    ties at theta are all extracted. (Local expansion is off: it would settle
+    the whole star in the source's step.)"""
+    N = 1000
+    rng = np.random.default_rng(27)
+    w = rng.permutation(N) + 1
+    g = graphgen.from_arcs(N + 1, np.zeros(N, dtype=np.int64), np.arange(1, N + 1), w)
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights, reorder=False)
+    for rho in (1, 7, 64, 999, 1000):
+        dist, st = sp.solve(G, [0], rule="rho_exact", rho=rho, trace=4096, tuning=NO_LOCAL)
+        assert_same(sp.to_numpy_u64(dist)[0], ref(g, 0), f"star rho {rho}")
+        ext = [r["extracted"] for r in st["trace"]]
+        assert ext[0] == 1 and sum(ext) == N + 1, (rho, ext[:5])
+        qs = [r["q"] for r in st["trace"]]
+        for r, q in zip(st["trace"][1:], qs[1:]):
+            assert r["extracted"] == min(rho, q), (rho, r)
+            assert bool(r["flags"] & 8) == (q > rho)
+    G.close()
+    # Ties: weights 1..10 each used 100 times; rho = 150 lands inside the
+    # second weight class, so the step takes every leaf of weights 1 and 2.
+    w = np.repeat(np.arange(1, 11), 100)
+    g = graphgen.from_arcs(1001, np.zeros(1000, dtype=np.int64), np.arange(1, 1001), w)
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights, reorder=False)
+    dist, st = sp.solve(G, [0], rule="rho_exact", rho=150, trace=64, tuning=NO_LOCAL)
+    assert_same(sp.to_numpy_u64(dist)[0], ref(g, 0), "star ties")
+    assert st["trace"][1]["extracted"] == 200 and st["trace"][1]["theta"] == 2
+    G.close()
 
 
 def test_seeds_and_repeats_agree(sp):
