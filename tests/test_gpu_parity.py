@@ -499,7 +499,7 @@ def test_full_rmat24_rho_sweep(sp, rmat24):
     s = int(rmat24.sources[0])
     exp = ref(g, s)
     G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
-    for rho in (1 << 16, 1 << 20, 1 << 22):
+    for rho in (1 << 16, 1 << 18, 1 << 22):  # 2^18: the benchmark's setting
         dist, st = sp.solve(G, [s], rule="rho", rho=rho)
         got = sp.to_numpy_u64(dist)[0]
         assert_same(got, exp, f"rmat24 rho=2^{rho.bit_length() - 1}")
@@ -520,10 +520,30 @@ def test_full_road5000_delta_star_and_bf(sp, road5000):
     s = int(road5000.sources[0])
     exp = ref(g, s)
     G = sp.Graph.from_csr(g.offsets.astype(np.int32), g.targets, g.weights)
-    for rule, kw in [("delta", {"delta": 1 << 10}), ("delta", {"delta": 1 << 13}), ("delta", {"delta": 1 << 16}),
+    for rule, kw in [("delta", {"delta": 1 << 10}), ("delta", {"delta": 1 << 15}), ("delta", {"delta": 1 << 16}),
                      ("bf", {})]:
         dist, st = sp.solve(G, [s], rule=rule, **kw)
         got = sp.to_numpy_u64(dist)[0]
         assert_same(got, exp, f"road5000 {rule} {kw}")
         print(f"road5000 {rule} {kw} steps={st['steps']} ms={st['device_ms']:.1f}", flush=True)
+    G.close()
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_full_knn10000_batched_rows(sp):
+    """The batched benchmark configuration: 64 sources on the 10^7-point kNN
+    graph in one launch. Four rows against the oracle, every row against the
+    linear-time certificate."""
+    w = graphgen.workload("knn10000", sources=64)
+    g = w.graph
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights, reorder=False)
+    for rule, kw in [("rho", {"rho": 4096}), ("delta", {"delta": 1 << 11})]:
+        dist, st = sp.solve(G, w.sources, rule=rule, **kw)
+        got = sp.to_numpy_u64(dist)
+        print(f"knn10000 {rule} {kw}: teams={st['teams']} ms={st['device_ms']:.1f}", flush=True)
+        for i in (0, 21, 42, 63):
+            assert_same(got[i], ref(g, w.sources[i]), f"knn10000 {rule} row {i}")
+        for i, s in enumerate(w.sources):
+            assert oracle.certificate(g.offsets, g.targets, g.weights, int(s), got[i]) == (0, -1), (rule, i)
     G.close()
