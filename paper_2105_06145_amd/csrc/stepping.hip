@@ -1,11 +1,14 @@
 // Persistent stepping-loop kernel for single-source shortest paths on
-// MI355X (gfx950), and sssp_solve of the C ABI (include/sssp.h).
+// MI355X (gfx950), and the solve and serving entry points of the C ABI
+// (include/sssp.h).
 //
-// One cooperative launch runs Alg. 1 (Sec. 3.2) for every requested source:
+// One persistent launch (cooperative for sssp_solve) runs Alg. 1 (Sec. 3.2)
+// for every requested source:
 //
 //   S0 init      delta[.] = inf, bitmap = 0; delta[s] = 0, Update(s).
 //   S1 ExtDist   theta per Table 2: rho-th smallest by sampling (Sec. 6,
-//                App. B), i * Delta (Delta*), +inf (Bellman-Ford), min (test).
+//                App. B) or by an exact radix selection, i * Delta (Delta*),
+//                +inf (Bellman-Ford), min (test).
 //   S2 Extract   F = {v in Q : delta[v] <= theta}; their queue flags cleared
 //                (Table 1). Q is a bitmap (the flat-array LaB-PQ of Sec. 4.3)
 //                plus, while |Q| is small, an explicit list (Sec. 6, sparse
@@ -25,6 +28,11 @@
 //                each new member once, with no hash table or pack pass.
 //   S5 loop      until |Q| = 0. Phases are separated by barriers, so Extract
 //                never overlaps Update (Sec. 3.1).
+//
+// Sec. 6's road-graph optimisations sit inside S3: local expansion (a
+// workgroup relaxes the vertices its WriteMins bring under theta itself, hop
+// after hop, in super-sparse steps) and bidirectional relaxation (pull the
+// best key from the neighbours before pushing; symmetric graphs only).
 //
 // Teams. The grid is split into `nteams` teams; team t is the workgroups b
 // with b % nteams == t. Each team repeatedly takes the next unsolved source
@@ -1498,7 +1506,8 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
           while (top > 0) {
             const int width = top < 8 ? top : 8;
             const int shift = top - width;
-            phase_select(a, dist, Lcur, q, dense, false, top, shift, (1ull << width) - 1, ld_agent(&tm.ctl->sel_prefix));
+            const ull prefix = ld_agent(&tm.ctl->sel_prefix);
+            phase_select(a, dist, Lcur, q, dense, false, top, shift, (1ull << width) - 1, prefix);
             auto pick = [&]() {
               if (tid == 0) select_serial(tm.ctl, false, shift, 0);
             };
