@@ -8,7 +8,9 @@ This module searches them by timing real solves on the device:
 
   1. the rule parameter, from large to small (large values mean few steps,
      small ones many; the time is taken to fall and then rise along the way,
-     so the sweep stops once two values in a row are slower than the best):
+     so the sweep stops once two values in a row are more than 5% slower
+     than the best; a flat stretch, such as rho above every queue size, does
+     not stop it):
      rho over powers of four from n down to 2^8, Delta over the median arc
      weight times powers of four; then the neighbouring powers of two;
   2. for batches, the number of teams the persistent grid is split into;
@@ -134,7 +136,7 @@ class Tuner:
                 if (out_of_time() and best[0] is not None) or worse >= 2:
                     break
                 scores[v] = self._eval({"rule": rule, name: v, "tuning": dict(base_tuning)}, best)
-                worse = worse + 1 if scores[v] > min(scores.values()) else 0
+                worse = worse + 1 if scores[v] > 1.05 * min(scores.values()) else 0
             if not scores:
                 continue
             v0 = min(scores, key=scores.get)

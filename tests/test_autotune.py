@@ -58,6 +58,19 @@ def test_sweep_stops_after_two_slower_values():
     assert set(sweep[6:8]) == {1 << 17, 1 << 19}
 
 
+def test_sweep_crosses_a_flat_stretch():
+    # Every rho above 2^16 behaves alike (noise within 2%); the optimum is at 2^10.
+    def model(cfg):
+        if "rho" not in cfg:
+            return 1.0
+        lg = math.log2(cfg["rho"])
+        noise = 0.02 * ((int(lg) * 7919) % 3 - 1)
+        return 100.0 * (1 + noise) if lg > 16 else 10 + (lg - 10) ** 2
+
+    cfg = at.Tuner(measure=model).search(n=1 << 24, nsrc=1, w_median=1, rules=("rho",))
+    assert cfg["rho"] == 1 << 10
+
+
 def test_search_single_source_has_no_teams_and_obeys_budget():
     tu = at.Tuner(measure=cost_model, budget_s=60)
     cfg = tu.search(n=1 << 16, nsrc=1, w_median=1 << 12, rules=("delta",))
