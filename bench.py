@@ -7,10 +7,16 @@ factor 16 (a = 0.57, b = 0.19, c = 0.19), symmetrised and deduplicated,
 weights uniform in [1, 2^18), one source in the largest component,
 rho-stepping. The graph is resident in HBM before timing starts.
 
+The default line also carries `latency`: a short serving run (R-MAT scale 22
+and a 2000x2000 road grid resident, Poisson arrivals) with p50/p99 of the
+serving launches against a one-query-at-a-time loop (`--latency-queries 0`
+skips it).
+
 `--workload knn10000` times the many-query workload instead: a 10-NN graph
 of 10^7 points in 1000 Gaussian clusters and 64 sources, all solved in one
 launch (a step = one batch of 64 queries), next to the same 64 queries
-solved one launch at a time.
+solved one launch at a time. `--workload serve` runs the serving comparison
+at full length; `road5000` and `grid256` time single solves.
 
 Prints one JSON line. `value` is edges relaxed per second (GTEPS, counting
 repeated relaxations) over the K timed steps; `roofline` prices the
@@ -343,7 +349,12 @@ def run_serve(args, torch, sp):
     # Parameters: tuned on a batch of the trace's sources per graph (served),
     # and on 8 single queries per graph (plain).
     cfg_s, cfg_p = [], []
-    for k in (0, 1):
+    if args.tune_budget <= 0:
+        # Settings a full tuning run of this workload chose (served: batches of
+        # 32 queries; plain: one query at a time on the whole grid).
+        cfg_s = [{"rule": "rho", "rho": 1 << 14, "tuning": {}}, {"rule": "delta", "delta": 8448, "tuning": {}}]
+        cfg_p = [{"rule": "rho", "rho": 1 << 17, "tuning": {}}, {"rule": "delta", "delta": 67584, "tuning": {}}]
+    for k in ((0, 1) if args.tune_budget > 0 else ()):
         ks = [int(x) for x in src[which == k][:32]]
         tb = at.Tuner(budget_s=args.tune_budget / 2)
         cfg_s.append(tb.tune(G[k], ks, rules=("rho",) if k == 0 else ("delta",)))
@@ -504,13 +515,16 @@ def main():
                     help="e.g. 16,17,18,19,20,21,22: time 3 solves per rho first and use the fastest")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--queries", type=int, default=600, help="serving: queries in the trace")
+    ap.add_argument("--latency-queries", type=int, default=200,
+                    help="rmat24: queries of the short serving run whose p50/p99 join the line (0 = skip)")
     ap.add_argument("--rows", type=int, default=64, help="serving: result rows (admission slots) per graph")
     ap.add_argument("--serve-teams", default="8,32",
                     help="serving: teams of the R-MAT and grid servers (each server has 2 workgroups per CU: "
                          "8 teams = 64 workgroups per query, 32 = 16)")
     ap.add_argument("--oracle-sample", type=int, default=4, help="serving: queries per graph checked by the oracle")
     ap.add_argument("--tune-budget", type=float, default=20.0,
-                    help="seconds of parameter search per mode for the batched workload (0 = workload defaults)")
+                    help="seconds of parameter search per mode for the batched and serving workloads "
+                         "(0 = the workload defaults, or for serving the settings of an earlier full search)")
     ap.add_argument("--cpu-settle-cap", type=int, default=0,
                     help="stop the CPU oracle after this many settled vertices (0 = full solve)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -554,6 +568,20 @@ def main():
         res = run_batched(args, torch, sp, w)
     else:
         res = run_single(args, torch, sp, w)
+        if args.workload == "rmat24" and args.latency_queries > 0:
+            # The metric's latency half: a short serving run (both graphs of the
+            # serving workload resident) against the one-at-a-time loop.
+            del w
+            la = argparse.Namespace(**vars(args))
+            la.queries, la.tune_budget, la.oracle_sample = args.latency_queries, 0.0, 1
+            try:
+                srv = run_serve(la, torch, sp)
+                res["latency"] = {k: srv[k] for k in ("closed_loop", "open_loop", "same_alone_and_in_the_mix",
+                                                       "oracle_checked")}
+                res["latency"]["workload"] = srv["config"]["workload"]
+                res["latency"]["queries"] = la.queries
+            except Exception as e:  # the throughput line above stands on its own
+                res["latency"] = {"error": f"{type(e).__name__}: {e}"}
     print(json.dumps(res), flush=True)
 
 
