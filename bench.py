@@ -407,31 +407,45 @@ def run_serve(args, torch, sp):
         waiting = [[], []]  # arrived, not yet admitted (per graph, FIFO)
         nxt = done = 0
         start = time.perf_counter()
-        last_log = start
-        while done < nq:
-            if time.perf_counter() - last_log > 5.0:
-                last_log = time.perf_counter()
-                log(f"  served: {done}/{nq} queries, {last_log - start:.1f}s")
-            now = time.perf_counter() - start
-            while nxt < nq and arrive[nxt] <= now:
-                waiting[int(which[nxt])].append(nxt)
-                nxt += 1
-            for k in (0, 1):
-                S = servers[k]
-                while waiting[k] and free[k]:
-                    i = waiting[k].pop(0)
-                    r = free[k].pop()
-                    ticket[k][S.submit(int(src[i]), r)] = (i, r)
-                for t, h in S.poll():
-                    i, r = ticket[k].pop(t)
-                    lat[i] = time.perf_counter() - start - arrive[i]
-                    hashes[i] = h
-                    free[k].append(r)
-                    done += 1
-        makespan = time.perf_counter() - start
-        stats = [S.stop() for S in servers]
-        for S in servers:
-            S.close()
+        last_log = last_done = start
+        try:
+            while done < nq:
+                now_abs = time.perf_counter()
+                if now_abs - last_log > 5.0:
+                    last_log = now_abs
+                    log(f"  served: {done}/{nq} queries, {now_abs - start:.1f}s")
+                if now_abs - last_done > 60.0:
+                    # Both servers must be resident at once; a tool that runs
+                    # kernels one at a time (a counter-collecting profiler)
+                    # leaves the second waiting for the first to go idle.
+                    raise RuntimeError(f"serving stalled at {done}/{nq} queries")
+                now = now_abs - start
+                while nxt < nq and arrive[nxt] <= now:
+                    waiting[int(which[nxt])].append(nxt)
+                    nxt += 1
+                for k in (0, 1):
+                    S = servers[k]
+                    while waiting[k] and free[k]:
+                        i = waiting[k].pop(0)
+                        r = free[k].pop()
+                        ticket[k][S.submit(int(src[i]), r)] = (i, r)
+                    for t, h in S.poll():
+                        i, r = ticket[k].pop(t)
+                        lat[i] = time.perf_counter() - start - arrive[i]
+                        hashes[i] = h
+                        free[k].append(r)
+                        done += 1
+                        last_done = time.perf_counter()
+            makespan = time.perf_counter() - start
+            stats = [S.stop() for S in servers]
+        finally:
+            for S in servers:
+                try:
+                    S.stop()
+                except Exception:
+                    pass
+            for S in servers:
+                S.close()
         return lat, hashes, makespan, stats
 
     # Closed loop: everything queued at t = 0.
