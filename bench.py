@@ -392,12 +392,13 @@ def run_serve(args, torch, sp):
 
     nrows = args.rows
     serve_teams = [int(x) for x in args.serve_teams.split(",")]
+    serve_bpc = [int(x) for x in args.serve_bpc.split(",")]
     rows = [torch.empty((nrows, g.n), dtype=torch.int64, device="cuda") for g in graphs]
 
     def served_loop(arrive):
         """Both graphs' servers running; queries admitted in arrival order as
         rows free up; returns (latencies, hashes, makespan, stats)."""
-        servers = [sp.Server(G[k], rows[k], tuning={**(cfg_s[k].get("tuning") or {}), "blocks_per_cu": 2,
+        servers = [sp.Server(G[k], rows[k], tuning={**(cfg_s[k].get("tuning") or {}), "blocks_per_cu": serve_bpc[k],
                                                     "teams": serve_teams[k]}, hash_rows=True,
                              ring_capacity=2 * nrows, stream=side, **params(cfg_s[k])) for k in (0, 1)]
         free = [list(range(nrows)), list(range(nrows))]
@@ -493,7 +494,7 @@ def run_serve(args, torch, sp):
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": WORKLOADS["serve"], "queries": nq, "rows_per_graph": nrows,
-                   "server_teams": serve_teams, "server_blocks_per_cu": 2,
+                   "server_teams": serve_teams, "server_blocks_per_cu": serve_bpc,
                    "served": [params(c) | {"tuning": c.get("tuning")} for c in cfg_s],
                    "plain": [params(c) | {"tuning": c.get("tuning")} for c in cfg_p]},
         "closed_loop": {"plain_qps": round(rate_plain, 2), "served_qps": round(nq / span_s0, 2),
@@ -532,9 +533,11 @@ def main():
     ap.add_argument("--latency-queries", type=int, default=200,
                     help="rmat24: queries of the short serving run whose p50/p99 join the line (0 = skip)")
     ap.add_argument("--rows", type=int, default=64, help="serving: result rows (admission slots) per graph")
-    ap.add_argument("--serve-teams", default="8,32",
-                    help="serving: teams of the R-MAT and grid servers (each server has 2 workgroups per CU: "
-                         "8 teams = 64 workgroups per query, 32 = 16)")
+    ap.add_argument("--serve-bpc", default="3,1",
+                    help="serving: workgroups per CU of the R-MAT and grid servers (sum at most 4)")
+    ap.add_argument("--serve-teams", default="8,8",
+                    help="serving: teams of the R-MAT and grid servers (with --serve-bpc 3,1 on 256 CUs: 8 "
+                         "R-MAT teams of 96 workgroups, 8 grid teams of 32)")
     ap.add_argument("--oracle-sample", type=int, default=4, help="serving: queries per graph checked by the oracle")
     ap.add_argument("--tune-budget", type=float, default=20.0,
                     help="seconds of parameter search per mode for the batched and serving workloads "
