@@ -563,12 +563,28 @@ __device__ __noinline__ ull wg_select_kth(const ull* vals, ull s, ull k) {
 // ---------------------------------------------------------------------------
 // Phase helpers.
 
-// Record one extracted hub vertex: its arcs become chunk tasks shared by the
-// team in Relax, each carrying the key the vertex was extracted with.
-__device__ __noinline__ void push_hub(const KArgs& a, ull* H, StepSlot* S, int32_t v, ull d) {
-  const ull deg = (ull)(a.off[v + 1] - a.off[v]);
-  const ull nch = (deg + a.chunk_edges - 1) / a.chunk_edges;
-  const ull base = atom_add(&S->h_count, nch);
+// Record the extracted hub vertices of a wave (lanes with is_hub set): their
+// arcs become chunk tasks shared by the team in Relax, each carrying the key
+// the vertex was extracted with. The wave reserves its tasks with one atomic
+// (hubs are numbered first, so they crowd into the same words and waves, and
+// one atomic per hub on the step's single counter would serialise). Whole
+// wave, uniform call.
+__device__ __noinline__ void wave_push_hubs(const KArgs& a, ull* H, StepSlot* S, bool is_hub, int32_t v, ull d) {
+  if (!__ballot(is_hub)) return;
+  const unsigned lane = lane_id();
+  ull nch = 0;
+  if (is_hub) {
+    const ull deg = (ull)(a.off[v + 1] - a.off[v]);
+    nch = (deg + a.chunk_edges - 1) / a.chunk_edges;
+  }
+  ull incl = nch;
+  for (int o = 1; o < 64; o <<= 1) {
+    const ull y = __shfl_up(incl, o);
+    if ((int)lane >= o) incl += y;
+  }
+  ull base = 0;
+  if (lane == 63) base = atom_add(&S->h_count, incl);  // lane 63 holds the wave's total
+  base = __shfl(base, 63) + incl - nch;
   for (ull c = 0; c < nch; ++c) {
     H[2 * (base + c)] = ((ull)(uint32_t)v << 32) | c;
     H[2 * (base + c) + 1] = d;
@@ -673,7 +689,7 @@ __device__ __forceinline__ void extract_round(const KArgs& a, const Team& tm, St
   const uint32_t first = o.fcnt + wg_scan(sh, ncand, total);
   const ull room = a.segcap - o.fcnt;
   uint32_t slot = first;
-  unsigned keep = 0;
+  unsigned keep = 0, hub_taken = 0;
   int32_t ev[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -698,13 +714,17 @@ __device__ __forceinline__ void extract_round(const KArgs& a, const Team& tm, St
       }
       ++o.x;
       if (a.xcount) ev[k] = v[k];
-      if ((hubs >> k) & 1u) push_hub(a, tm.H, S, v[k], d[k]);
+      if ((hubs >> k) & 1u) hub_taken |= 1u << k;
     } else {
       o.minkept = umin(o.minkept, d[k]);
       keep |= 1u << k;
     }
   }
   o.fcnt += (uint32_t)umin((ull)total, room);
+  if (__ballot(hub_taken != 0)) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) wave_push_hubs(a, tm.H, S, (hub_taken >> k) & 1u, v[k], d[k]);
+  }
   if (emit) list_append(a, S, Lnext, v, keep);
   if (a.xcount) {
     uint32_t* xc = a.xcount + ld_agent(&tm.ctl->query) * (ull)a.n;
@@ -755,8 +775,9 @@ __device__ __noinline__ ExtractOut phase_extract_dense(const KArgs& a, const ull
 }
 
 // S2, bitmap step without an explicit list to build. Each lane owns words as
-// above and walks its members on its own (no workgroup barrier), reserving F
-// slots with an LDS counter.
+// above and walks its members with no workgroup barrier, reserving F slots
+// with an LDS counter; rounds are wave-uniform so that extracted hubs are
+// recorded with one atomic per wave.
 __device__ __noinline__ ExtractOut phase_extract_dense_fast(const KArgs& a, const ull* dist, StepSlot* S,
                                                             ull theta) {
   const Team& tm = g_tm;
@@ -771,12 +792,10 @@ __device__ __noinline__ ExtractOut phase_extract_dense_fast(const KArgs& a, cons
   for (ull r0 = tm.rank; r0 < nblocks; r0 += T * BLOCKS_PER_ROUND) {
     const ull blk = r0 + T * (threadIdx.x / BLOCK_WORDS);
     const ull wi = blk * BLOCK_WORDS + (threadIdx.x % BLOCK_WORDS);
-    if (blk >= nblocks || wi >= nw) continue;
-    const ull word = ld_agent(&tm.bitmap[wi]);
-    if (!word) continue;
-    const ull hubw = ld_plain(&a.hubmask[wi]);
+    const ull word = (blk < nblocks && wi < nw) ? ld_agent(&tm.bitmap[wi]) : 0ull;
+    const ull hubw = word ? ld_plain(&a.hubmask[wi]) : 0ull;
     ull rest = word, clear = 0;
-    while (rest) {
+    while (__ballot(rest != 0)) {
       int32_t v[BATCH];
       ull d[BATCH];
 #pragma unroll
@@ -790,6 +809,7 @@ __device__ __noinline__ ExtractOut phase_extract_dense_fast(const KArgs& a, cons
       }
 #pragma unroll
       for (int k = 0; k < BATCH; ++k) d[k] = v[k] >= 0 ? ld_agent(&dist[v[k]]) : INF;
+      unsigned hub_taken = 0;
 #pragma unroll
       for (int k = 0; k < BATCH; ++k) {
         if (v[k] < 0) continue;
@@ -797,7 +817,7 @@ __device__ __noinline__ ExtractOut phase_extract_dense_fast(const KArgs& a, cons
         bool ext = d[k] <= theta;
         if (ext) {
           if ((hubw & bit) != 0) {
-            push_hub(a, tm.H, S, v[k], d[k]);
+            hub_taken |= 1u << k;
           } else {
             const uint32_t slot = atomicAdd(&sh.fcnt, 1u);
             if (slot < a.segcap) {
@@ -816,8 +836,84 @@ __device__ __noinline__ ExtractOut phase_extract_dense_fast(const KArgs& a, cons
           o.minkept = umin(o.minkept, d[k]);
         }
       }
+      if (__ballot(hub_taken != 0)) {
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k) wave_push_hubs(a, tm.H, S, (hub_taken >> k) & 1u, v[k], d[k]);
+      }
     }
-    if (clear) tm.bitmap[wi] = word & ~clear;
+    if (clear) tm.bitmap[wi] = word & ~clear;  // this lane owns word wi
+  }
+  __syncthreads();
+  o.fcnt = (uint32_t)umin((ull)sh.fcnt, a.segcap);
+  return o;
+}
+
+// S2, bitmap step without an explicit list, when at least a quarter of the
+// vertices are queued: a lane walking the members of a crowded word issues
+// dozens of dependent loads, so here wave w of the workgroup takes word w of
+// each owned block and lane l looks at bit l; the keys of a word's members
+// come in one coalesced load. WPI words are in flight per wave. F slots are
+// reserved per wave and word with one LDS atomic; the owner wave writes the
+// word back without the extracted bits.
+constexpr int WPI = 4;
+
+__device__ __noinline__ ExtractOut phase_extract_dense_words(const KArgs& a, const ull* dist, StepSlot* S,
+                                                             ull theta) {
+  const Team& tm = g_tm;
+  Shared& sh = g_sh;
+  const ull nw = a.nwords, T = tm.T;
+  const ull nblocks = (nw + BLOCK_WORDS - 1) / BLOCK_WORDS;
+  const unsigned lane = lane_id(), wave = threadIdx.x >> 6;
+  const ull below_lane = (1ull << lane) - 1ull;
+  ExtractOut o{0, 0, INF};
+  if (threadIdx.x == 0) sh.fcnt = 0;
+  __syncthreads();
+  uint32_t* xc = a.xcount ? a.xcount + ld_agent(&tm.ctl->query) * (ull)a.n : nullptr;
+  for (ull blk0 = tm.rank; blk0 < nblocks; blk0 += (ull)WPI * T) {
+    ull wi[WPI], word[WPI], d[WPI], hubw[WPI];
+#pragma unroll
+    for (int k = 0; k < WPI; ++k) {
+      const ull blk = blk0 + (ull)k * T;
+      wi[k] = blk * BLOCK_WORDS + wave;
+      word[k] = (blk < nblocks && wi[k] < nw) ? ld_agent(&tm.bitmap[wi[k]]) : 0ull;
+    }
+#pragma unroll
+    for (int k = 0; k < WPI; ++k) {
+      d[k] = ((word[k] >> lane) & 1ull) ? ld_agent(&dist[wi[k] * 64 + lane]) : INF;
+      hubw[k] = word[k] ? ld_plain(&a.hubmask[wi[k]]) : 0ull;
+    }
+#pragma unroll
+    for (int k = 0; k < WPI; ++k) {
+      if (!word[k]) continue;  // the same word in every lane
+      const int32_t v = (int32_t)(wi[k] * 64 + lane);
+      const bool member = (word[k] >> lane) & 1ull;
+      const bool hub = (hubw[k] >> lane) & 1ull;
+      bool ext = member && d[k] <= theta;
+      const ull want = __ballot(ext && !hub);
+      if (want) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&sh.fcnt, (uint32_t)__popcll(want));
+        base = __shfl(base, 0);
+        if (ext && !hub) {
+          const uint32_t slot = base + (uint32_t)__popcll(want & below_lane);
+          if (slot < a.segcap) {
+            tm.Fb[slot] = v;
+            if (a.snapshot) tm.FDb[slot] = d[k];
+          } else {
+            ext = false;  // no room: stays queued
+          }
+        }
+      }
+      wave_push_hubs(a, tm.H, S, ext && hub, v, d[k]);
+      if (ext) {
+        ++o.x;
+        if (xc) xc[a.perm ? a.perm[v] : v] += 1u;
+      } else if (member) {
+        o.minkept = umin(o.minkept, d[k]);
+      }
+      const ull taken = __ballot(ext);
+      if (taken && lane == 0) tm.bitmap[wi[k]] = word[k] & ~taken;  // this wave owns word wi
+    }
   }
   __syncthreads();
   o.fcnt = (uint32_t)umin((ull)sh.fcnt, a.segcap);
@@ -1543,9 +1639,10 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
       }
 
       // ---- S2: Extract(theta) over this workgroup's slice ----
-      const ExtractOut ex = !dense  ? phase_extract_list(a, dist, S, Lcur, Lnext, q, theta, emit)
-                            : emit ? phase_extract_dense(a, dist, S, Lnext, theta, emit)
-                                   : phase_extract_dense_fast(a, dist, S, theta);
+      const ExtractOut ex = !dense       ? phase_extract_list(a, dist, S, Lcur, Lnext, q, theta, emit)
+                            : emit        ? phase_extract_dense(a, dist, S, Lnext, theta, emit)
+                            : q * 4 >= n  ? phase_extract_dense_words(a, dist, S, theta)
+                                          : phase_extract_dense_fast(a, dist, S, theta);
       if (!team_sync(a, sh, tm, NoSerial{})) return;
       ph2 += lap();
       const long long t_relax = wall_clock64();
