@@ -171,6 +171,7 @@ struct KArgs {
   ull* dist_out;        // caller's rows, n_src x n, caller ids
   ull* dist_int;        // per-team internal rows (relabelled graphs), else NULL
   ull* bitmap;          // per team, nwords
+  uint32_t* hint;       // per team, n: upper bound of each key for the Relax filter (NULL: no filter)
   int32_t* F;           // per workgroup, segcap: extracted vertices
   ull* FD;              // per workgroup, segcap: their keys when extracted
   ull* H;               // per team, hcap pairs: ((vertex << 32) | chunk index, key)
@@ -238,6 +239,7 @@ struct Team {
   ull id, rank, T;  // team index, rank in the team, team size
   TeamCtl* ctl;
   ull* bitmap;
+  uint32_t* hint;
   ull* H;
   int32_t* L;
   ull* samples;
@@ -592,12 +594,23 @@ __device__ __noinline__ void wave_push_hubs(const KArgs& a, ull* H, StepSlot* S,
 }
 
 // WriteMin(delta[v], nd) (S3). Returns true when it lowered delta[v].
-// Filter: a plain read of delta[v] (possibly stale, but never smaller than
-// the current value) showing nd >= delta[v] means the WriteMin cannot succeed,
-// so the atomic is skipped.
-__device__ __forceinline__ bool writemin(const KArgs& a, ull* dist, int32_t v, ull nd) {
-  if (a.filter && !(nd < ld_plain(&dist[v]))) return false;
-  return nd < atom_min(&dist[v], nd);
+// Filter: hint[v] is a 32-bit upper bound of delta[v] (HINT_NONE: none
+// known), kept by the successful WriteMins with plain stores; a stale hint is
+// still an upper bound, since keys only fall. nd >= hint[v] means the WriteMin
+// cannot succeed, so the atomic is skipped. The hints take half the cache
+// lines of the keys, and this read is the one random read of every arc.
+constexpr uint32_t HINT_NONE = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t as_hint(ull d) { return d < (ull)HINT_NONE ? (uint32_t)d : HINT_NONE; }
+
+__device__ __forceinline__ bool writemin(uint32_t* hint, ull* dist, int32_t v, ull nd) {
+  if (hint) {
+    const uint32_t h = (uint32_t)ld_plain(&hint[v]);
+    if (h != HINT_NONE && nd >= (ull)h) return false;
+  }
+  if (!(nd < atom_min(&dist[v], nd))) return false;
+  if (hint) hint[v] = as_hint(nd);
+  return true;
 }
 
 // Update(v) (S4): set v's flag; true when v is new to Q.
@@ -981,7 +994,7 @@ __device__ __forceinline__ void relax_batch(const KArgs& a, const Team& tm, ull*
     if (ev[k] == INF) continue;
     ++acc.edges;
     const ull nd = dd[k] + (ev[k] >> 32);
-    if (!writemin(a, dist, fv[k], nd)) continue;
+    if (!writemin(tm.hint, dist, fv[k], nd)) continue;
     ++acc.succ;
     // Hubs go to Q, where their arcs are split over the team.
     if (lx.on && nd <= lx.theta && !((ld_plain(&a.hubmask[fv[k] >> 6]) >> (fv[k] & 63)) & 1ull)) {
@@ -1455,6 +1468,7 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
   tm.T = a.G / a.nteams;
   tm.ctl = a.teams + tm.id;
   tm.bitmap = a.bitmap + tm.id * a.nwords;
+  tm.hint = a.hint ? a.hint + tm.id * (ull)a.n : nullptr;
   tm.H = a.H + tm.id * 2 * a.hcap;
   tm.L = a.L + tm.id * 2 * a.lcap;
   tm.samples = a.samples + tm.id * a.probe_cap;
@@ -1537,6 +1551,8 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
 
     // S0: delta = inf, Q empty; then delta[s] = 0 and Update(s).
     for (ull i = tm.rank * WG + tid; i < n; i += tm.T * WG) dist[i] = INF;
+    if (tm.hint)
+      for (ull i = tm.rank * WG + tid; i < n; i += tm.T * WG) tm.hint[i] = HINT_NONE;
     for (ull i = tm.rank * WG + tid; i < a.nwords; i += tm.T * WG) tm.bitmap[i] = 0;
     {
       auto seed_source = [&]() {
@@ -1548,6 +1564,7 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
           const int32_t src = a.serve ? (int32_t)tm.ctl->src : a.srcs[qi];
           const int32_t s = a.inv ? a.inv[src] : src;
           dist[s] = 0;
+          if (tm.hint) tm.hint[s] = 0;
           tm.bitmap[s >> 6] = 1ull << (s & 63);
           tm.L[0] = s;
         }
@@ -1781,6 +1798,7 @@ sssp_status ensure_workspace(sssp_graph* g, const sssp_tuning& tu, const Geometr
   const uint64_t n = (uint64_t)g->n, nt = geo.nteams;
   if (g->relabelled) SSSP_HIP_TRY(g->dist_int.alloc(nt * n * 8, st));
   SSSP_HIP_TRY(g->bitmap.alloc(nt * geo.nwords * 8, st));
+  SSSP_HIP_TRY(g->hint.alloc(nt * n * 4, st));
   SSSP_HIP_TRY(g->hubmask.alloc(geo.nwords * 8, st));
   SSSP_HIP_TRY(g->F.alloc((uint64_t)geo.G * geo.segcap * 4, st));
   SSSP_HIP_TRY(g->FD.alloc((uint64_t)geo.G * geo.segcap * 8, st));
@@ -1907,6 +1925,7 @@ sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uin
   a.sample_cap = tu.sample_cap;
   a.probe_cap = tu.probe_cap;
   a.filter = tu.no_filter ? 0u : 1u;
+  a.hint = tu.no_filter ? nullptr : (uint32_t*)g->hint.p;
   a.snapshot = (p.flags & SSSP_SOLVE_SNAPSHOT_KEYS) ? 1u : 0u;
   // Local expansion reads current keys, so snapshot-key runs go without it.
   a.local_budget = (a.snapshot || tu.local_budget == 0xFFFFFFFFu) ? 0u : tu.local_budget;
