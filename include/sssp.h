@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define SSSP_ABI_VERSION 1
+#define SSSP_ABI_VERSION 2
 
 typedef enum {
   SSSP_OK = 0,
@@ -53,7 +53,8 @@ typedef enum {
   SSSP_ERR_NO_DEVICE = 4,        /* no HIP device, or it cannot run a cooperative launch */
   SSSP_ERR_DEVICE = 5,           /* a HIP runtime call or the kernel failed */
   SSSP_ERR_STEP_LIMIT = 6,       /* params.max_steps steps ran and the queue is not empty */
-  SSSP_ERR_UNSUPPORTED = 7       /* a valid request this build does not implement */
+  SSSP_ERR_UNSUPPORTED = 7,      /* a valid request this build does not implement */
+  SSSP_ERR_CANCELLED = 8         /* an asynchronous solve stopped by sssp_solve_cancel */
 } sssp_status;
 
 /* Threshold rules (ExtDist of Alg. 1; Table 2). Every rule yields the same
@@ -229,7 +230,7 @@ sssp_status sssp_graph_create(int64_t n, int64_t m, sssp_offset_width ow, const 
 
 /* Release the graph and its device memory. NULL is accepted. Must not race a
  * solve on the same graph; refused (INVALID_ARGUMENT) while a server runs on
- * it. */
+ * it or an asynchronous solve is pending (sssp_solve_wait first). */
 sssp_status sssp_graph_destroy(sssp_graph* g);
 
 /* Query sizes: vertices, arcs and device bytes held (graph plus workspace). */
@@ -253,6 +254,39 @@ sssp_status sssp_graph_info(const sssp_graph* g, int64_t* n, int64_t* m, uint64_
  */
 sssp_status sssp_solve(const sssp_graph* g, const int32_t* sources, int32_t n_src, const sssp_params* params,
                        uint64_t* dist, void* stream, sssp_stats* stats);
+
+/*
+ * Stream-ordered form of sssp_solve: the same computation (Alg. 1 per source,
+ * all sources in one launch), for callers that overlap it with other work.
+ * The call enqueues the launch on `stream` and returns without waiting. `sources` and `params` are
+ * read before it returns (sources are copied); `dist` is complete once the
+ * stream reaches the end of the launch, so work enqueued after it on the same
+ * stream may read it. One asynchronous solve may be pending per graph; until
+ * sssp_solve_wait returns, sssp_solve, sssp_solve_async, sssp_server_start
+ * and sssp_graph_destroy on the graph return INVALID_ARGUMENT.
+ * Errors at enqueue time as for sssp_solve; errors of the run itself come
+ * from sssp_solve_wait.
+ */
+sssp_status sssp_solve_async(const sssp_graph* g, const int32_t* sources, int32_t n_src,
+                             const sssp_params* params, uint64_t* dist, void* stream);
+
+/* Whether the pending asynchronous solve has finished on the device: *done =
+ * 1 or 0 (never blocks). INVALID_ARGUMENT when none is pending. */
+sssp_status sssp_solve_query(const sssp_graph* g, int* done);
+
+/* Wait for the pending asynchronous solve and end it: stats (host pointer or
+ * NULL) as for sssp_solve, and its status: OK, STEP_LIMIT, DEVICE, or
+ * CANCELLED (then the rows of sources whose solve was under way hold upper
+ * bounds of the distances, and rows of sources not yet started are left
+ * unwritten). INVALID_ARGUMENT when none is pending. */
+sssp_status sssp_solve_wait(const sssp_graph* g, sssp_stats* stats);
+
+/* Ask the pending asynchronous solve to stop early: the kernel reads a flag in
+ * host memory once per step (in the step's last barrier) and every team
+ * leaves at the end of its current step. Returns at once; sssp_solve_wait
+ * then reports CANCELLED unless the solve had already finished. INVALID_ARGUMENT
+ * when none is pending. */
+sssp_status sssp_solve_cancel(const sssp_graph* g);
 
 /*
  * Order-independent checksum of a distance row: the sum over v of a 64-bit

@@ -23,14 +23,16 @@ from ._native import (SSSP_RULE_BF, SSSP_RULE_DELTA_STAR, SSSP_RULE_MIN, SSSP_RU
                       sssp_abi_version,
                       sssp_default_params, sssp_graph_create, sssp_graph_destroy, sssp_graph_info,
                       sssp_last_error, sssp_params, sssp_row_hash, sssp_server_destroy, sssp_server_poll,
-                      sssp_server_start, sssp_server_stop, sssp_server_submit, sssp_solve, sssp_stats,
+                      sssp_server_start, sssp_server_stop, sssp_server_submit, sssp_solve, sssp_solve_async,
+                      sssp_solve_cancel, sssp_solve_query, sssp_solve_wait, sssp_stats,
                       sssp_status_string, sssp_step_record, sssp_tuning)
 
-__all__ = ["Graph", "solve", "Server", "row_hash", "SSSPError", "to_numpy_u64", "RULES", "INF", "sssp_graph_create",
+__all__ = ["Graph", "solve", "solve_async", "PendingSolve", "Server", "row_hash", "SSSPError", "to_numpy_u64", "RULES", "INF", "sssp_graph_create",
            "sssp_graph_destroy", "sssp_graph_info", "sssp_solve", "sssp_status_string", "sssp_last_error",
            "sssp_abi_version", "sssp_default_params", "sssp_params", "sssp_stats", "sssp_tuning",
            "sssp_step_record", "sssp_row_hash", "sssp_server_start", "sssp_server_submit", "sssp_server_poll",
-           "sssp_server_stop", "sssp_server_destroy"]
+           "sssp_server_stop", "sssp_server_destroy", "sssp_solve_async", "sssp_solve_query", "sssp_solve_wait",
+           "sssp_solve_cancel"]
 
 INF = 0xFFFFFFFFFFFFFFFF
 RULES = {"rho": SSSP_RULE_RHO, "rho_exact": SSSP_RULE_RHO_EXACT, "delta": SSSP_RULE_DELTA_STAR,
@@ -231,6 +233,60 @@ def solve(g: Graph, sources, rule: str = "rho", rho: int = 1 << 20, delta: int =
                          "local": int(r[6]), "extract_ns": int(r[7]), "relax_ns": int(r[8])})
         stats["trace"] = recs
     return out, stats
+
+
+class PendingSolve:
+    """An asynchronous solve (sssp_solve_async): `out` is complete once the
+    stream reaches the end of the launch; wait() returns (out, stats) and ends
+    it, cancel() asks it to stop early (wait() then raises SSSPError with
+    status SSSP_ERR_CANCELLED unless it had already finished)."""
+
+    def __init__(self, g: Graph, out, keep):
+        self.g, self.out, self._keep, self._open = g, out, keep, True
+
+    def done(self) -> bool:
+        rc, d = sssp_solve_query(self.g._h)
+        if rc != N.SSSP_OK:
+            raise SSSPError(rc, "sssp_solve_query")
+        return bool(d)
+
+    def cancel(self):
+        if self._open:
+            rc = sssp_solve_cancel(self.g._h)
+            if rc != N.SSSP_OK:
+                raise SSSPError(rc, "sssp_solve_cancel")
+
+    def wait(self):
+        if not self._open:
+            raise RuntimeError("already waited")
+        st = sssp_stats()
+        rc = sssp_solve_wait(self.g._h, st)
+        self._open = False
+        self._keep = None
+        if rc != N.SSSP_OK:
+            raise SSSPError(rc, "sssp_solve_wait")
+        return self.out, st.as_dict()
+
+
+def solve_async(g: Graph, sources, rule: str = "rho", rho: int = 1 << 20, delta: int = 1 << 13, seed: int = 1,
+                max_steps: int = 0, tuning: dict | sssp_tuning | None = None, out=None,
+                stream=None) -> PendingSolve:
+    """Enqueue a solve on `stream` (default: the current torch stream) and
+    return at once; see PendingSolve."""
+    torch = _torch()
+    src = np.ascontiguousarray(np.atleast_1d(np.asarray(sources)), dtype=np.int32)
+    ns = int(src.shape[0])
+    if out is None:
+        out = torch.empty((ns, g.n), dtype=torch.int64, device="cuda")
+    elif out.dtype != torch.int64 or out.numel() != ns * g.n or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int64 CUDA tensor with n_src * n elements")
+    p, tun = _params(rule, rho, delta, seed, tuning)
+    p.max_steps = int(max_steps)
+    rc = sssp_solve_async(g._h, ctypes.c_void_p(src.ctypes.data), ns, p, ctypes.c_void_p(out.data_ptr()),
+                          _stream_ptr(stream))
+    if rc != N.SSSP_OK:
+        raise SSSPError(rc, "sssp_solve_async")
+    return PendingSolve(g, out, (p, tun))
 
 
 def row_hash(row, stream=None) -> int:

@@ -29,6 +29,7 @@ SSSP_ERR_NO_DEVICE = 4
 SSSP_ERR_DEVICE = 5
 SSSP_ERR_STEP_LIMIT = 6
 SSSP_ERR_UNSUPPORTED = 7
+SSSP_ERR_CANCELLED = 8
 
 # Rules (sssp_rule)
 SSSP_RULE_RHO = 0
@@ -121,6 +122,14 @@ def lib():
         L.sssp_solve.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(sssp_params), vp, vp,
                                  ctypes.POINTER(sssp_stats)]
         L.sssp_solve.restype = ctypes.c_int
+        L.sssp_solve_async.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(sssp_params), vp, vp]
+        L.sssp_solve_async.restype = ctypes.c_int
+        L.sssp_solve_query.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+        L.sssp_solve_query.restype = ctypes.c_int
+        L.sssp_solve_wait.argtypes = [vp, ctypes.POINTER(sssp_stats)]
+        L.sssp_solve_wait.restype = ctypes.c_int
+        L.sssp_solve_cancel.argtypes = [vp]
+        L.sssp_solve_cancel.restype = ctypes.c_int
         L.sssp_status_string.argtypes = [ctypes.c_int]
         L.sssp_status_string.restype = ctypes.c_char_p
         L.sssp_last_error.argtypes = []
@@ -176,6 +185,26 @@ def sssp_graph_info(handle):
 def sssp_solve(handle, sources_ptr, n_src, params: sssp_params, dist_ptr, stream_ptr, stats: sssp_stats | None):
     return lib().sssp_solve(handle, sources_ptr, int(n_src), ctypes.byref(params) if params is not None else None,
                             dist_ptr, stream_ptr, ctypes.byref(stats) if stats is not None else None)
+
+
+def sssp_solve_async(handle, sources_ptr, n_src, params: sssp_params, dist_ptr, stream_ptr):
+    return lib().sssp_solve_async(handle, sources_ptr, int(n_src),
+                                  ctypes.byref(params) if params is not None else None, dist_ptr, stream_ptr)
+
+
+def sssp_solve_query(handle):
+    """Returns (status, done)."""
+    d = ctypes.c_int()
+    rc = lib().sssp_solve_query(handle, ctypes.byref(d))
+    return rc, d.value
+
+
+def sssp_solve_wait(handle, stats: sssp_stats | None):
+    return lib().sssp_solve_wait(handle, ctypes.byref(stats) if stats is not None else None)
+
+
+def sssp_solve_cancel(handle):
+    return lib().sssp_solve_cancel(handle)
 
 
 def sssp_row_hash(dist_ptr, n, stream_ptr):

@@ -199,6 +199,7 @@ const char* sssp_status_string(sssp_status s) {
     case SSSP_ERR_DEVICE: return "device error";
     case SSSP_ERR_STEP_LIMIT: return "step limit reached";
     case SSSP_ERR_UNSUPPORTED: return "unsupported";
+    case SSSP_ERR_CANCELLED: return "cancelled";
   }
   return "unknown status";
 }
@@ -208,6 +209,7 @@ const char* sssp_last_error(void) { return last_error().c_str(); }
 sssp_status sssp_graph_destroy(sssp_graph* g) {
   if (!g) return SSSP_OK;
   if (g->serving) return fail(SSSP_ERR_INVALID_ARGUMENT, "a server is running on this graph; stop it first");
+  if (g->pending) return fail(SSSP_ERR_INVALID_ARGUMENT, "an asynchronous solve is pending; sssp_solve_wait first");
   (void)hipSetDevice(g->device);
   g->release_all();
   delete g;

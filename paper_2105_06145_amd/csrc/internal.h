@@ -70,6 +70,10 @@ struct sssp_graph {
   bool relabelled = false;
   bool undirected = false;  // every arc (u, v, w) has its reverse (v, u, w)
   bool serving = false;  // a persistent server owns the workspace
+  void* pending = nullptr;          // the pending asynchronous solve (owned by stepping.hip)
+  uint32_t* cancel_flag = nullptr;  // host (hipHostMalloc): nonzero asks the pending solve to stop
+  int32_t* src_host = nullptr;      // host (hipHostMalloc): staged sources of an asynchronous solve
+  uint64_t src_host_cap = 0;
   // Workspace.
   bool ws_ready = false;
   uint32_t ws_hub_degree = 0, ws_chunk = 0, ws_probe_cap = 0, ws_G = 0, ws_teams = 0;
@@ -90,6 +94,11 @@ struct sssp_graph {
   }
   void release_all() {
     release_ws(nullptr);
+    if (cancel_flag) (void)hipHostFree(cancel_flag);
+    if (src_host) (void)hipHostFree(src_host);
+    cancel_flag = nullptr;
+    src_host = nullptr;
+    src_host_cap = 0;
     off.release(nullptr);
     edges.release(nullptr);
     perm.release(nullptr);

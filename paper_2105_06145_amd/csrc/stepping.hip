@@ -140,11 +140,12 @@ struct GridCtl {
   Line next_query;
   Line mismatch;  // some workgroup is not on the XCD its index implies
   alignas(128) unsigned abort_flag;
-  unsigned pad0;
+  unsigned cancelled;  // some team saw the host's cancel flag: teams claim no more sources
   ull ngroups;
 };
 
 constexpr unsigned ST_STEP_LIMIT = 1;
+constexpr unsigned ST_CANCELLED = 2;
 
 // Per-workgroup partial counts of one step.
 struct alignas(64) Part {
@@ -212,6 +213,7 @@ struct KArgs {
   uint64_t ring_cap;
   uint64_t nrows;              // rows of dist_out
   uint64_t idle_ticks;         // longest wait for a request
+  const uint32_t* cancel;      // host: nonzero asks the solve to stop (asynchronous solves), or NULL
 };
 
 constexpr ull SERVE_EXIT = ~0ull;
@@ -1533,7 +1535,7 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
       if (a.serve) {
         serve_claim(a, tm.ctl, gc);
       } else {
-        tm.ctl->query = atom_add(&gc->next_query.v, 1ull);
+        tm.ctl->query = (a.cancel && ld_agent(&gc->cancelled)) ? (ull)a.n_src : atom_add(&gc->next_query.v, 1ull);
       }
     };
     if (a.serve) {
@@ -1672,9 +1674,14 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
       const unsigned flags = (dense ? 1u : 0u) | (emit ? 2u : 0u) | (sampled ? 4u : 0u) | (exact ? 8u : 0u);
       auto bookkeeping = [&]() {
         step_bookkeeping(a, S, t, q, theta, flags, (ull)(t_relax - t_step), (ull)t_relax);
+        if (a.cancel && tid == 0 && ld_system(a.cancel) != 0u) {
+          tm.ctl->status |= ST_CANCELLED;
+          __hip_atomic_store(&gc->cancelled, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
       };
       if (!team_sync(a, sh, tm, bookkeeping)) return;
       ph3 += lap();
+      if (a.cancel && (ld_agent(&tm.ctl->status) & ST_CANCELLED)) break;
 
       // ---- S5: next queue state, identical in every workgroup of the team ----
       q = q - ld_agent(&S->x_total) + ld_agent(&S->fresh_total);
@@ -1947,7 +1954,7 @@ hipError_t stage_launch(sssp_graph* g, const Launch& L, hipStream_t st) {
 // Read the control blocks back (after the kernel finished) into stats.
 // Returns the abort and step-limit indications.
 sssp_status collect_stats(sssp_graph* g, const Launch& L, hipStream_t st, sssp_stats* stats, bool& aborted,
-                          bool& step_limit) {
+                          bool& step_limit, bool& cancelled) {
   GridCtl hg;
   std::string hteams((size_t)L.nteams * sizeof(TeamCtl), '\0');
   SSSP_HIP_TRY(hipMemcpyAsync(&hg, g->ctl.p, sizeof(GridCtl), hipMemcpyDeviceToHost, st));
@@ -1956,10 +1963,12 @@ sssp_status collect_stats(sssp_graph* g, const Launch& L, hipStream_t st, sssp_s
   SSSP_HIP_TRY(hipStreamSynchronize(st));
   aborted = hg.abort_flag != 0;
   step_limit = false;
+  cancelled = false;
   for (uint32_t t = 0; t < L.nteams; ++t) {
     TeamCtl tc;
     std::memcpy(&tc, &hteams[(size_t)t * sizeof(TeamCtl)], sizeof(TeamCtl));
     step_limit |= (tc.status & ST_STEP_LIMIT) != 0;
+    cancelled |= (tc.status & ST_CANCELLED) != 0;
     if (!stats) continue;
     stats->steps += tc.st_steps;
     stats->extracted += tc.st_extracted;
@@ -1989,6 +1998,78 @@ __global__ void row_hash_kernel(const ull* dist, ull n, ull* out) {
   h = wave_sum(h);
   if (lane_id() == 0) atom_add(out, h);
 }
+
+// Checks, workspace and the kernel launch of a solve (shared by the
+// synchronous and the asynchronous entry points). `src_stage` is a host copy
+// of the sources that stays valid until the copy has run (the caller's array
+// for a synchronous solve, the graph's pinned staging array otherwise).
+sssp_status enqueue_solve(sssp_graph* g, const int32_t* sources, int32_t n_src,
+                          uint64_t* dist, hipStream_t st, const uint32_t* cancel, Launch& L, hipEvent_t ev0,
+                          hipEvent_t ev1) {
+  {
+    // The default team count needs the grid size, which prepare_launch
+    // computes; resolve it there through a provisional value.
+    int occ = 0;
+    SSSP_HIP_TRY(hipSetDevice(g->device));
+    SSSP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, stepping_kernel, WG, 0));
+    const uint32_t G = std::max(1u, std::min<uint32_t>(L.tu.blocks_per_cu, (uint32_t)std::max(occ, 1))) *
+                       (uint32_t)g->cus;
+    sssp_status s = prepare_launch(g, L, auto_teams(n_src, G), dist, st);
+    if (s != SSSP_OK) return s;
+  }
+  if ((uint64_t)n_src > g->ws_src_cap) {
+    SSSP_HIP_TRY(g->srcs.alloc((uint64_t)n_src * 4, st));
+    g->ws_src_cap = (uint64_t)n_src;
+  }
+  L.a.srcs = (const int32_t*)g->srcs.p;
+  L.a.n_src = n_src;
+  L.a.cancel = cancel;
+  hipError_t e = hipMemcpyAsync(g->srcs.p, sources, (size_t)n_src * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = stage_launch(g, L, st);
+  if (e == hipSuccess) e = hipEventRecord(ev0, st);
+  if (e == hipSuccess) {
+    const KArgs* dargs = (const KArgs*)g->args.p;
+    void* kargs[] = {(void*)&dargs};
+    e = hipLaunchCooperativeKernel((const void*)stepping_kernel, dim3(L.G), dim3(WG), kargs, 0, st);
+  }
+  if (e == hipSuccess) e = hipEventRecord(ev1, st);
+  if (e != hipSuccess) return fail(from_hip(e), std::string("solve: ") + hipGetErrorString(e));
+  return SSSP_OK;
+}
+
+// After the launch has finished: stats and the run's status.
+sssp_status finish_solve(sssp_graph* g, const Launch& L, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                         sssp_stats* stats) {
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, ev0, ev1);
+  bool aborted = false, step_limit = false, cancelled = false;
+  sssp_status cs = collect_stats(g, L, st, stats, aborted, step_limit, cancelled);
+  if (cs != SSSP_OK) return cs;
+  if (stats) stats->device_ms = ms;
+  if (aborted) return fail(SSSP_ERR_DEVICE, "grid barrier timed out (workgroups not co-resident?)");
+  if (cancelled) return fail(SSSP_ERR_CANCELLED, "solve cancelled");
+  if (step_limit) return fail(SSSP_ERR_STEP_LIMIT, "max_steps reached with a non-empty queue");
+  return SSSP_OK;
+}
+
+sssp_status check_solve_args(const sssp_graph* gc, const int32_t* sources, int32_t n_src, uint64_t* dist) {
+  if (!gc) return fail(SSSP_ERR_INVALID_ARGUMENT, "graph is NULL");
+  if (gc->serving) return fail(SSSP_ERR_INVALID_ARGUMENT, "a server is running on this graph");
+  if (gc->pending) return fail(SSSP_ERR_INVALID_ARGUMENT, "an asynchronous solve is pending on this graph");
+  if (n_src < 0) return fail(SSSP_ERR_INVALID_ARGUMENT, "n_src < 0");
+  if (n_src > 0 && (!sources || !dist)) return fail(SSSP_ERR_INVALID_ARGUMENT, "sources or dist is NULL");
+  for (int32_t i = 0; i < n_src; ++i)
+    if (sources[i] < 0 || sources[i] >= gc->n)
+      return fail(SSSP_ERR_INVALID_ARGUMENT, "source " + std::to_string(sources[i]) + " out of range");
+  return SSSP_OK;
+}
+
+// An asynchronous solve between sssp_solve_async and sssp_solve_wait.
+struct PendingSolve {
+  Launch L;
+  hipStream_t st = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
 
 }  // namespace
 
@@ -2032,63 +2113,118 @@ void sssp_default_params(sssp_params* p) {
 sssp_status sssp_solve(const sssp_graph* gc, const int32_t* sources, int32_t n_src, const sssp_params* params,
                        uint64_t* dist, void* stream, sssp_stats* stats) {
   last_error().clear();
-  if (!gc) return fail(SSSP_ERR_INVALID_ARGUMENT, "graph is NULL");
-  if (gc->serving) return fail(SSSP_ERR_INVALID_ARGUMENT, "a server is running on this graph");
-  if (n_src < 0) return fail(SSSP_ERR_INVALID_ARGUMENT, "n_src < 0");
-  if (n_src > 0 && (!sources || !dist)) return fail(SSSP_ERR_INVALID_ARGUMENT, "sources or dist is NULL");
+  sssp_status as = check_solve_args(gc, sources, n_src, dist);
+  if (as != SSSP_OK) return as;
   Launch L;
   sssp_status ps = check_params(params, L.p, L.tu);
   if (ps != SSSP_OK) return ps;
-  for (int32_t i = 0; i < n_src; ++i)
-    if (sources[i] < 0 || sources[i] >= gc->n)
-      return fail(SSSP_ERR_INVALID_ARGUMENT, "source " + std::to_string(sources[i]) + " out of range");
   if (stats) std::memset(stats, 0, sizeof(*stats));
   if (n_src == 0) return SSSP_OK;
 
   sssp_graph* g = const_cast<sssp_graph*>(gc);
   hipStream_t st = (hipStream_t)stream;
-  {
-    // The default team count needs the grid size, which prepare_launch
-    // computes; resolve it there through a provisional value.
-    int occ = 0;
-    SSSP_HIP_TRY(hipSetDevice(g->device));
-    SSSP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, stepping_kernel, WG, 0));
-    const uint32_t G = std::max(1u, std::min<uint32_t>(L.tu.blocks_per_cu, (uint32_t)std::max(occ, 1))) *
-                       (uint32_t)g->cus;
-    sssp_status s = prepare_launch(g, L, auto_teams(n_src, G), dist, st);
-    if (s != SSSP_OK) return s;
-  }
-  if ((uint64_t)n_src > g->ws_src_cap) {
-    SSSP_HIP_TRY(g->srcs.alloc((uint64_t)n_src * 4, st));
-    g->ws_src_cap = (uint64_t)n_src;
-  }
-  L.a.srcs = (const int32_t*)g->srcs.p;
-  L.a.n_src = n_src;
-
   hipEvent_t ev0, ev1;
   SSSP_HIP_TRY(hipEventCreate(&ev0));
   SSSP_HIP_TRY(hipEventCreate(&ev1));
-  hipError_t e = hipMemcpyAsync(g->srcs.p, sources, (size_t)n_src * 4, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = stage_launch(g, L, st);
-  if (e == hipSuccess) e = hipEventRecord(ev0, st);
-  if (e == hipSuccess) {
-    const KArgs* dargs = (const KArgs*)g->args.p;
-    void* kargs[] = {(void*)&dargs};
-    e = hipLaunchCooperativeKernel((const void*)stepping_kernel, dim3(L.G), dim3(WG), kargs, 0, st);
+  sssp_status s = enqueue_solve(g, sources, n_src, dist, st, nullptr, L, ev0, ev1);
+  if (s == SSSP_OK) {
+    const hipError_t e = hipStreamSynchronize(st);
+    s = e == hipSuccess ? finish_solve(g, L, st, ev0, ev1, stats)
+                        : fail(from_hip(e), std::string("solve: ") + hipGetErrorString(e));
   }
-  if (e == hipSuccess) e = hipEventRecord(ev1, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  float ms = 0;
-  if (e == hipSuccess) (void)hipEventElapsedTime(&ms, ev0, ev1);
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
-  if (e != hipSuccess) return fail(from_hip(e), std::string("solve: ") + hipGetErrorString(e));
-  bool aborted = false, step_limit = false;
-  sssp_status cs = collect_stats(g, L, st, stats, aborted, step_limit);
-  if (cs != SSSP_OK) return cs;
-  if (stats) stats->device_ms = ms;
-  if (aborted) return fail(SSSP_ERR_DEVICE, "grid barrier timed out (workgroups not co-resident?)");
-  if (step_limit) return fail(SSSP_ERR_STEP_LIMIT, "max_steps reached with a non-empty queue");
+  return s;
+}
+
+sssp_status sssp_solve_async(const sssp_graph* gc, const int32_t* sources, int32_t n_src,
+                             const sssp_params* params, uint64_t* dist, void* stream) {
+  last_error().clear();
+  sssp_status as = check_solve_args(gc, sources, n_src, dist);
+  if (as != SSSP_OK) return as;
+  if (n_src == 0) return fail(SSSP_ERR_INVALID_ARGUMENT, "an asynchronous solve needs at least one source");
+  auto* P = new (std::nothrow) PendingSolve;
+  if (!P) return fail(SSSP_ERR_OUT_OF_MEMORY, "pending-solve record");
+  sssp_status ps = check_params(params, P->L.p, P->L.tu);
+  if (ps != SSSP_OK) {
+    delete P;
+    return ps;
+  }
+  sssp_graph* g = const_cast<sssp_graph*>(gc);
+  hipError_t e = hipSetDevice(g->device);
+  // Pinned staging for the sources and the cancel flag: the caller may
+  // reuse its array once this call returns.
+  if (e == hipSuccess && !g->cancel_flag) e = hipHostMalloc((void**)&g->cancel_flag, 64, hipHostMallocCoherent);
+  if (e == hipSuccess && (uint64_t)n_src > g->src_host_cap) {
+    if (g->src_host) (void)hipHostFree(g->src_host);
+    g->src_host = nullptr;
+    g->src_host_cap = 0;
+    e = hipHostMalloc((void**)&g->src_host, (size_t)n_src * 4, hipHostMallocDefault);
+    if (e == hipSuccess) g->src_host_cap = (uint64_t)n_src;
+  }
+  if (e == hipSuccess) e = hipEventCreate(&P->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&P->ev1);
+  if (e != hipSuccess) {
+    if (P->ev0) (void)hipEventDestroy(P->ev0);
+    if (P->ev1) (void)hipEventDestroy(P->ev1);
+    delete P;
+    return fail(from_hip(e), std::string("solve_async: ") + hipGetErrorString(e));
+  }
+  std::memcpy(g->src_host, sources, (size_t)n_src * 4);
+  __atomic_store_n(g->cancel_flag, 0u, __ATOMIC_SEQ_CST);
+  P->st = (hipStream_t)stream;
+  sssp_status s = enqueue_solve(g, g->src_host, n_src, dist, P->st, g->cancel_flag, P->L, P->ev0, P->ev1);
+  if (s != SSSP_OK) {
+    // Whatever was enqueued must finish before the staging memory is reused.
+    (void)hipStreamSynchronize(P->st);
+    (void)hipEventDestroy(P->ev0);
+    (void)hipEventDestroy(P->ev1);
+    delete P;
+    return s;
+  }
+  g->pending = P;
+  return SSSP_OK;
+}
+
+sssp_status sssp_solve_query(const sssp_graph* gc, int* done) {
+  last_error().clear();
+  if (!gc || !done) return fail(SSSP_ERR_INVALID_ARGUMENT, "graph or done is NULL");
+  if (!gc->pending) return fail(SSSP_ERR_INVALID_ARGUMENT, "no asynchronous solve is pending");
+  const auto* P = static_cast<const PendingSolve*>(gc->pending);
+  const hipError_t e = hipEventQuery(P->ev1);
+  if (e == hipSuccess) {
+    *done = 1;
+  } else if (e == hipErrorNotReady) {
+    *done = 0;
+  } else {
+    return fail(from_hip(e), std::string("solve_query: ") + hipGetErrorString(e));
+  }
+  return SSSP_OK;
+}
+
+sssp_status sssp_solve_wait(const sssp_graph* gc, sssp_stats* stats) {
+  last_error().clear();
+  if (!gc) return fail(SSSP_ERR_INVALID_ARGUMENT, "graph is NULL");
+  if (!gc->pending) return fail(SSSP_ERR_INVALID_ARGUMENT, "no asynchronous solve is pending");
+  sssp_graph* g = const_cast<sssp_graph*>(gc);
+  auto* P = static_cast<PendingSolve*>(g->pending);
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  (void)hipSetDevice(g->device);
+  const hipError_t e = hipEventSynchronize(P->ev1);
+  sssp_status s = e == hipSuccess ? finish_solve(g, P->L, P->st, P->ev0, P->ev1, stats)
+                                  : fail(from_hip(e), std::string("solve_wait: ") + hipGetErrorString(e));
+  (void)hipEventDestroy(P->ev0);
+  (void)hipEventDestroy(P->ev1);
+  delete P;
+  g->pending = nullptr;
+  return s;
+}
+
+sssp_status sssp_solve_cancel(const sssp_graph* gc) {
+  last_error().clear();
+  if (!gc) return fail(SSSP_ERR_INVALID_ARGUMENT, "graph is NULL");
+  if (!gc->pending || !gc->cancel_flag) return fail(SSSP_ERR_INVALID_ARGUMENT, "no asynchronous solve is pending");
+  __atomic_store_n(gc->cancel_flag, 1u, __ATOMIC_SEQ_CST);
   return SSSP_OK;
 }
 
@@ -2120,6 +2256,7 @@ sssp_status sssp_server_start(const sssp_graph* gc, const sssp_params* params, u
     return fail(SSSP_ERR_INVALID_ARGUMENT, "graph or dist_rows is NULL, or rows / ring_capacity is 0");
   if (flags & ~SSSP_SERVE_HASH) return fail(SSSP_ERR_INVALID_ARGUMENT, "unknown server flags");
   if (gc->serving) return fail(SSSP_ERR_INVALID_ARGUMENT, "a server is already running on this graph");
+  if (gc->pending) return fail(SSSP_ERR_INVALID_ARGUMENT, "an asynchronous solve is pending on this graph");
   sssp_graph* g = const_cast<sssp_graph*>(gc);
   sssp_server* s = new (std::nothrow) sssp_server;
   if (!s) return fail(SSSP_ERR_OUT_OF_MEMORY, "server");
@@ -2287,7 +2424,8 @@ sssp_status sssp_server_stop(sssp_server* s, sssp_stats* stats) {
       s->stop_status = fail(from_hip(e), std::string("server: ") + hipGetErrorString(e));
     } else {
       bool aborted = false, step_limit = false;
-      s->stop_status = collect_stats(s->g, s->L, s->st, &s->final_stats, aborted, step_limit);
+      bool cancelled = false;  // servers have no cancel flag
+      s->stop_status = collect_stats(s->g, s->L, s->st, &s->final_stats, aborted, step_limit, cancelled);
       float ms = 0;
       (void)hipEventElapsedTime(&ms, s->ev0, s->ev1);
       s->final_stats.device_ms = ms;

@@ -51,7 +51,7 @@ def test_struct_layouts_match_header(tmp_path):
 
 
 def test_version_strings_defaults():
-    assert N.sssp_abi_version() == 1
+    assert N.sssp_abi_version() == 2
     assert N.sssp_status_string(N.SSSP_OK) == "ok"
     assert "argument" in N.sssp_status_string(N.SSSP_ERR_INVALID_ARGUMENT)
     assert N.sssp_status_string(99) == "unknown status"
@@ -147,6 +147,17 @@ def test_serving_and_checksum_null_arguments():
     h = ctypes.c_uint64()
     assert lib.sssp_row_hash(None, 5, None, ctypes.byref(h)) == N.SSSP_ERR_INVALID_ARGUMENT
     assert "NULL" in N.sssp_last_error()
+
+
+def test_async_solve_null_arguments():
+    # Every check here returns before any device call.
+    p = N.sssp_default_params()
+    assert N.sssp_solve_async(None, None, 1, p, None, None) == N.SSSP_ERR_INVALID_ARGUMENT
+    assert "NULL" in N.sssp_last_error()
+    assert N.sssp_solve_query(None)[0] == N.SSSP_ERR_INVALID_ARGUMENT
+    assert N.sssp_solve_wait(None, None) == N.SSSP_ERR_INVALID_ARGUMENT
+    assert N.sssp_solve_cancel(None) == N.SSSP_ERR_INVALID_ARGUMENT
+    assert N.sssp_status_string(N.SSSP_ERR_CANCELLED) == "cancelled"
 
 
 def test_graph_create_rejects_unknown_flag_bits():
