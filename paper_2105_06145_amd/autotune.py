@@ -14,7 +14,8 @@ This module searches them by timing real solves on the device:
      rho over powers of four from n down to 2^8, Delta over the median arc
      weight times powers of four; then the neighbouring powers of two;
   2. for batches, the number of teams the persistent grid is split into;
-  3. the hub-degree threshold, then the explicit-list switch.
+  3. the hub-degree threshold, the size of the arc chunks hubs are cut into
+     (the tile shape of their relaxation), then the explicit-list switch.
 
 Each candidate is timed `reps` times (median of the kernel time). Results are
 cached per (graph fingerprint, batch-size class) in a JSON file, so a graph
@@ -59,7 +60,8 @@ def team_candidates(nsrc: int, grid: int = 1024) -> list[int]:
 
 
 class Tuner:
-    """Coordinate search over (rule parameter, teams, hub_degree, list_divisor).
+    """Coordinate search over (rule parameter, teams, hub_degree, chunk_edges,
+    list_divisor).
 
     `measure(config) -> ms` times one configuration; by default it runs the
     solver on the given graph and sources. A config is a dict with keys rule,
@@ -148,6 +150,7 @@ class Tuner:
         if nsrc > 1:
             knobs.append(("teams", team_candidates(nsrc, grid)))
         knobs.append(("hub_degree", [256, 1024, 4096]))
+        knobs.append(("chunk_edges", [1024, 4096, 16384]))
         knobs.append(("list_divisor", [16, 64, 256]))
         for knob, values in knobs:
             start = best[0]

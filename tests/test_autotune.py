@@ -11,7 +11,7 @@ from paper_2105_06145_amd import autotune as at
 
 def cost_model(cfg):
     """A made-up cost with its minimum at rho = 2^14 (or Delta = 4096),
-    teams = 32, hub_degree = 4096, list_divisor = 64."""
+    teams = 32, hub_degree = 4096, chunk_edges = 16384, list_divisor = 64."""
     t = cfg.get("tuning", {})
     if cfg["rule"] == "rho":
         c = 10 + (math.log2(cfg["rho"]) - 14) ** 2
@@ -20,6 +20,7 @@ def cost_model(cfg):
     teams = t.get("teams", 0) or 64  # 0: the library's choice for 40 sources
     c += 0 if teams == 32 else 1 + abs(math.log2(teams) - 5)
     c -= 0.5 if t.get("hub_degree") == 4096 else 0
+    c -= 0.125 if t.get("chunk_edges") == 16384 else 0
     c += 0 if t.get("list_divisor", 64) == 64 else 0.25
     return c
 
@@ -39,8 +40,9 @@ def test_search_finds_the_minimum_of_the_model():
     cfg = tu.search(n=1 << 20, nsrc=40, w_median=1000)
     assert cfg["rule"] == "rho" and cfg["rho"] == 1 << 14
     assert cfg["tuning"]["teams"] == 32 and cfg["tuning"]["hub_degree"] == 4096
+    assert cfg["tuning"]["chunk_edges"] == 16384
     assert cfg.get("tuning", {}).get("list_divisor", 64) == 64
-    assert cfg["ms"] == pytest.approx(9.5)
+    assert cfg["ms"] == pytest.approx(9.375)
     assert cfg["evaluations"] == len(tu.history)
 
 
