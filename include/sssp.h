@@ -130,6 +130,15 @@ typedef struct {
                              (INVALID_ARGUMENT on other graphs), 0xFFFFFFFF = off; always off
                              with SSSP_SOLVE_SNAPSHOT_KEYS */
   uint32_t reserved;
+  uint32_t queue;         /* LaB-PQ structure (Sec. 4): 0 = the flat array (a bitmap, plus an
+                             explicit list while the queue is small; Sec. 4.3, 6); 1 = a
+                             tournament tree (Sec. 4.2, Alg. 2) of fan-out 64 over the bitmap:
+                             each node keeps the smallest key queued below it, lowered with an
+                             atomic min on every successful WriteMin (Mark, stopping where a
+                             node already holds a smaller key) and recomputed by the workgroup
+                             that extracts below it; Extract descends only into nodes whose key
+                             is at most theta. Same extracted sets, so the same distances */
+  uint32_t reserved2;
 } sssp_tuning;
 
 /* One record per step, written when params.trace is set. */

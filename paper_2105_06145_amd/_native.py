@@ -56,7 +56,8 @@ class sssp_tuning(ctypes.Structure):
                 ("sample_cap", ctypes.c_uint32), ("probe_cap", ctypes.c_uint32),
                 ("no_filter", ctypes.c_uint32), ("teams", ctypes.c_uint32),
                 ("local_budget", ctypes.c_uint32), ("super_sparse_degree", ctypes.c_uint32),
-                ("pull", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("pull", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("queue", ctypes.c_uint32),
+                ("reserved2", ctypes.c_uint32)]
 
 
 class sssp_step_record(ctypes.Structure):

@@ -15,7 +15,8 @@ This module searches them by timing real solves on the device:
      weight times powers of four; then the neighbouring powers of two;
   2. for batches, the number of teams the persistent grid is split into;
   3. the hub-degree threshold, the size of the arc chunks hubs are cut into
-     (the tile shape of their relaxation), then the explicit-list switch.
+     (the tile shape of their relaxation), the explicit-list switch, then
+     the queue structure (flat array or tournament tree, Sec. 4).
 
 Each candidate is timed `reps` times (median of the kernel time). Results are
 cached per (graph fingerprint, batch-size class) in a JSON file, so a graph
@@ -152,6 +153,7 @@ class Tuner:
         knobs.append(("hub_degree", [256, 1024, 4096]))
         knobs.append(("chunk_edges", [1024, 4096, 16384]))
         knobs.append(("list_divisor", [16, 64, 256]))
+        knobs.append(("queue", [1]))
         for knob, values in knobs:
             start = best[0]
             for v in values:

@@ -173,6 +173,9 @@ struct KArgs {
   ull* dist_int;        // per-team internal rows (relabelled graphs), else NULL
   ull* bitmap;          // per team, nwords
   uint32_t* hint;       // per team, n: upper bound of each key for the Relax filter (NULL: no filter)
+  ull* key1;            // tournament-tree queue (NULL: flat array): per team, nwords (one node per bitmap word)
+  ull* key2;            // per team, n2 (one node per 64 words)
+  uint64_t n2;
   int32_t* F;           // per workgroup, segcap: extracted vertices
   ull* FD;              // per workgroup, segcap: their keys when extracted
   ull* H;               // per team, hcap pairs: ((vertex << 32) | chunk index, key)
@@ -201,6 +204,7 @@ struct KArgs {
   uint32_t ns_per_tick;   // wall-clock counter period
   uint32_t pull;          // bidirectional relaxation (undirected graphs)
   uint32_t super_sparse;  // local expansion in list steps below this average out-degree
+  uint64_t sparse_q;      // tournament-tree queue: steps with |Q| at most this count as list steps for local expansion
   // Serving mode: requests come from a ring in host memory instead of srcs.
   uint32_t serve;
   uint32_t hash;               // add each finished row's checksum to its ring entry
@@ -242,6 +246,8 @@ struct Team {
   TeamCtl* ctl;
   ull* bitmap;
   uint32_t* hint;
+  ull* key1;  // tournament tree (NULL: flat array)
+  ull* key2;
   ull* H;
   int32_t* L;
   ull* samples;
@@ -621,6 +627,34 @@ __device__ __forceinline__ bool mark(ull* bitmap, int32_t v) {
   return !(atom_or(&bitmap[v >> 6], bit) & bit);
 }
 
+// Tournament-tree queue (Sec. 4.2, Alg. 2), fan-out 64: node key1[w] holds
+// the smallest key queued in bitmap word w, key2[j] the smallest over words
+// 64j .. 64j + 63 (n2 = ceil(words / 64) of them). A workgroup that extracts
+// below a node relaxes what it extracted, and vertices are numbered by
+// decreasing degree, so in this mode every vertex above 64 arcs is relaxed
+// through the team's shared hub chunks instead (the launch lowers
+// hub_degree to 64), which keeps Relax balanced. Alg. 2's Mark sets "renewed" flags up the path and Update
+// recomputes those nodes before the next Extract; here the keys that Relax
+// can only lower are lowered at once with an atomic min (Mark's walk up,
+// which stops where a node already holds a smaller key, as Alg. 2's stops at
+// a flag already set), and the nodes that Extract raises are recomputed by
+// the workgroup that owns them during that Extract. A node may hold less than
+// the minimum below it (a lowered key whose vertex was not queued); Extract
+// then finds nothing there and sets the node exact. It never holds more, so
+// descending only into nodes with key <= theta finds every such vertex. A
+// plain read first skips the atomic when the node already holds a key <= d
+// (most WriteMins: the node is the minimum of 64 keys, and many WriteMins
+// land on the same few words, where atomics would serialise); a stale read
+// is never smaller than the node's key, so no lowering is lost.
+__device__ __forceinline__ void tree_lower(const Team& tm, int32_t v, ull d) {
+  if (!tm.key1) return;
+  ull* k1 = &tm.key1[v >> 6];
+  if (d < ld_plain(k1) && d < atom_min(k1, d)) {
+    ull* k2 = &tm.key2[v >> 12];
+    if (d < ld_plain(k2)) atom_min(k2, d);
+  }
+}
+
 // Append the flagged entries of each lane to the next explicit list with one
 // atomic per workgroup; entries past the list capacity are dropped (the
 // reserved count then exceeds the capacity and the list is not used).
@@ -935,6 +969,96 @@ __device__ __noinline__ ExtractOut phase_extract_dense_words(const KArgs& a, con
   return o;
 }
 
+// S2 with the tournament-tree queue: Traverse(theta) of Alg. 2 from the
+// second level. Team rank r owns the level-2 nodes r, r + T, ... and the
+// words below them; it skips a node whose key is above theta, and below a
+// node it visits, wave w takes the children w, w + 4, ... (words 64j + c): a child
+// with key above theta is skipped, otherwise the wave extracts its word as in
+// phase_extract_dense_words (lane l, bit l) and stores the word's new key
+// (the smallest key left in it). The node's key is then recomputed from its
+// 64 children. The keys of skipped nodes and of members left bound the keys
+// kept in Q.
+__device__ __noinline__ ExtractOut phase_extract_tree(const KArgs& a, const ull* dist, StepSlot* S, ull theta) {
+  const Team& tm = g_tm;
+  Shared& sh = g_sh;
+  const ull nw = a.nwords;
+  const unsigned lane = lane_id(), wave = threadIdx.x >> 6;
+  const ull below_lane = (1ull << lane) - 1ull;
+  ExtractOut o{0, 0, INF};
+  if (threadIdx.x == 0) sh.fcnt = 0;
+  __syncthreads();
+  uint32_t* xc = a.xcount ? a.xcount + ld_agent(&tm.ctl->query) * (ull)a.n : nullptr;
+  for (ull j = tm.rank; j < a.n2; j += tm.T) {
+    const ull k2 = ld_agent(&tm.key2[j]);  // the same in every lane
+    if (k2 > theta) {
+      o.minkept = umin(o.minkept, k2);
+      continue;
+    }
+    // Children c = wave + 4 i; four at a time, their loads issued together.
+    for (int i0 = 0; i0 < 64 / WAVES; i0 += 4) {
+      ull wi[4], k1[4], word[4], d[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        wi[k] = j * 64 + wave + (ull)WAVES * (i0 + k);
+        k1[k] = wi[k] < nw ? ld_agent(&tm.key1[wi[k]]) : INF;  // the same in every lane of the wave
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) word[k] = (wi[k] < nw && k1[k] <= theta) ? ld_agent(&tm.bitmap[wi[k]]) : 0ull;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) d[k] = ((word[k] >> lane) & 1ull) ? ld_agent(&dist[wi[k] * 64 + lane]) : INF;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (wi[k] >= nw) continue;
+        if (k1[k] > theta) {
+          o.minkept = umin(o.minkept, k1[k]);
+          continue;
+        }
+        const bool member = (word[k] >> lane) & 1ull;
+        const int32_t v = (int32_t)(wi[k] * 64 + lane);
+        const bool hub = member && ((ld_plain(&a.hubmask[wi[k]]) >> lane) & 1ull);
+        bool ext = member && d[k] <= theta;
+        const ull want = __ballot(ext && !hub);
+        if (want) {
+          uint32_t base = 0;
+          if (lane == 0) base = atomicAdd(&sh.fcnt, (uint32_t)__popcll(want));
+          base = __shfl(base, 0);
+          if (ext && !hub) {
+            const uint32_t slot = base + (uint32_t)__popcll(want & below_lane);
+            if (slot < a.segcap) {
+              tm.Fb[slot] = v;
+              if (a.snapshot) tm.FDb[slot] = d[k];
+            } else {
+              ext = false;  // no room: stays queued
+            }
+          }
+        }
+        wave_push_hubs(a, tm.H, S, ext && hub, v, d[k]);
+        if (ext) {
+          ++o.x;
+          if (xc) xc[a.perm ? a.perm[v] : v] += 1u;
+        }
+        const ull left = wave_min(member && !ext ? d[k] : INF);
+        o.minkept = umin(o.minkept, left);
+        const ull taken = __ballot(ext);
+        if (lane == 0) {
+          if (taken) tm.bitmap[wi[k]] = word[k] & ~taken;  // this wave owns word wi
+          tm.key1[wi[k]] = left;
+        }
+      }
+    }
+    __syncthreads();  // the children's new keys are written
+    if (wave == 0) {
+      const ull wi = j * 64 + lane;
+      const ull k = wave_min(wi < nw ? ld_agent(&tm.key1[wi]) : INF);
+      if (lane == 0) tm.key2[j] = k;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  o.fcnt = (uint32_t)umin((ull)sh.fcnt, a.segcap);
+  return o;
+}
+
 // S2, list step: this workgroup's contiguous slice of the explicit list.
 __device__ __noinline__ ExtractOut phase_extract_list(const KArgs& a, const ull* dist, StepSlot* S,
                                                       const int32_t* Lcur, int32_t* Lnext, ull q, ull theta,
@@ -998,6 +1122,7 @@ __device__ __forceinline__ void relax_batch(const KArgs& a, const Team& tm, ull*
     const ull nd = dd[k] + (ev[k] >> 32);
     if (!writemin(tm.hint, dist, fv[k], nd)) continue;
     ++acc.succ;
+    tree_lower(tm, fv[k], nd);
     // Hubs go to Q, where their arcs are split over the team.
     if (lx.on && nd <= lx.theta && !((ld_plain(&a.hubmask[fv[k] >> 6]) >> (fv[k] & 63)) & 1ull)) {
       const uint32_t slot = atomicAdd(&sh.lqn[lx.nxt], 1u);
@@ -1062,6 +1187,7 @@ __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* 
       // u's arcs are all pushed below with the lower key, so u need not
       // return to Q (a WriteMin of another workgroup on u still marks it).
       atom_min(&dist[u], sh.pulled[tid]);
+      tree_lower(tm, u, sh.pulled[tid]);  // u may have been queued again meanwhile
       sh.du[tid] = sh.pulled[tid];
       ++acc.succ;
     }
@@ -1128,6 +1254,7 @@ __device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S,
         unsigned m1 = 0;
         if (tid == 0 && best < atom_min(&dist[u], best)) {
           ++acc.succ;
+          tree_lower(tm, u, best);
           acc.minnew = umin(acc.minnew, best);
           if (mark(tm.bitmap, u)) {
             ++acc.fresh;
@@ -1471,6 +1598,8 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
   tm.ctl = a.teams + tm.id;
   tm.bitmap = a.bitmap + tm.id * a.nwords;
   tm.hint = a.hint ? a.hint + tm.id * (ull)a.n : nullptr;
+  tm.key1 = a.key1 ? a.key1 + tm.id * a.nwords : nullptr;
+  tm.key2 = a.key1 ? a.key2 + tm.id * a.n2 : nullptr;
   tm.H = a.H + tm.id * 2 * a.hcap;
   tm.L = a.L + tm.id * 2 * a.lcap;
   tm.samples = a.samples + tm.id * a.probe_cap;
@@ -1555,6 +1684,10 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
     for (ull i = tm.rank * WG + tid; i < n; i += tm.T * WG) dist[i] = INF;
     if (tm.hint)
       for (ull i = tm.rank * WG + tid; i < n; i += tm.T * WG) tm.hint[i] = HINT_NONE;
+    if (tm.key1) {
+      for (ull i = tm.rank * WG + tid; i < a.nwords; i += tm.T * WG) tm.key1[i] = INF;
+      for (ull i = tm.rank * WG + tid; i < a.n2; i += tm.T * WG) tm.key2[i] = INF;
+    }
     for (ull i = tm.rank * WG + tid; i < a.nwords; i += tm.T * WG) tm.bitmap[i] = 0;
     {
       auto seed_source = [&]() {
@@ -1567,6 +1700,10 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
           const int32_t s = a.inv ? a.inv[src] : src;
           dist[s] = 0;
           if (tm.hint) tm.hint[s] = 0;
+          if (tm.key1) {
+            tm.key1[s >> 6] = 0;
+            tm.key2[s >> 12] = 0;
+          }
           tm.bitmap[s >> 6] = 1ull << (s & 63);
           tm.L[0] = s;
         }
@@ -1658,7 +1795,8 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
       }
 
       // ---- S2: Extract(theta) over this workgroup's slice ----
-      const ExtractOut ex = !dense       ? phase_extract_list(a, dist, S, Lcur, Lnext, q, theta, emit)
+      const ExtractOut ex = tm.key1      ? phase_extract_tree(a, dist, S, theta)
+                            : !dense       ? phase_extract_list(a, dist, S, Lcur, Lnext, q, theta, emit)
                             : emit        ? phase_extract_dense(a, dist, S, Lnext, theta, emit)
                             : q * 4 >= n  ? phase_extract_dense_words(a, dist, S, theta)
                                           : phase_extract_dense_fast(a, dist, S, theta);
@@ -1669,7 +1807,8 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
       // ---- S3/S4: Relax + Update ----
       // Local expansion in super-sparse steps: list steps whose previous
       // step relaxed fewer than super_sparse arcs per vertex on average.
-      const bool local = a.local_budget && !dense && prev_e < (ull)a.super_sparse * umin(prev_x, INF / 64);
+      const bool sparse = tm.key1 ? q <= a.sparse_q : !dense;
+      const bool local = a.local_budget && sparse && prev_e < (ull)a.super_sparse * umin(prev_x, INF / 64);
       phase_relax(a, dist, S, Lnext, emit, ex, local, theta);
       const unsigned flags = (dense ? 1u : 0u) | (emit ? 2u : 0u) | (sampled ? 4u : 0u) | (exact ? 8u : 0u);
       auto bookkeeping = [&]() {
@@ -1783,6 +1922,11 @@ Geometry make_geometry(const sssp_graph* g, const sssp_tuning& tu, uint32_t G, u
   // steps) or of its list slice (list steps, at most ceil(n / T)).
   const uint64_t nblocks = (geo.nwords + BLOCK_WORDS - 1) / BLOCK_WORDS;
   geo.segcap = 64ull * BLOCK_WORDS * ((nblocks + geo.T - 1) / geo.T);
+  if (tu.queue == 1) {
+    // Tournament tree: a workgroup owns whole level-2 nodes of 4096 vertices.
+    const uint64_t n2 = (geo.nwords + 63) / 64;
+    geo.segcap = std::max<uint64_t>(geo.segcap, 4096ull * ((n2 + geo.T - 1) / geo.T));
+  }
   // Each vertex is extracted at most once per step and an extracted hub
   // contributes ceil(deg / chunk) tasks: m / chunk + m / (hub_degree + 1) + 1
   // bounds the tasks of one step.
@@ -1799,13 +1943,14 @@ uint64_t control_words(uint32_t nteams) { return (sizeof(GridCtl) + (uint64_t)nt
 
 sssp_status ensure_workspace(sssp_graph* g, const sssp_tuning& tu, const Geometry& geo, hipStream_t st) {
   if (g->ws_ready && g->ws_hub_degree == tu.hub_degree && g->ws_chunk == tu.chunk_edges &&
-      g->ws_probe_cap >= tu.probe_cap && g->ws_G == geo.G && g->ws_teams == geo.nteams)
+      g->ws_probe_cap >= tu.probe_cap && g->ws_G == geo.G && g->ws_teams == geo.nteams && g->ws_segcap == geo.segcap)
     return SSSP_OK;
   g->release_ws(st);
   const uint64_t n = (uint64_t)g->n, nt = geo.nteams;
   if (g->relabelled) SSSP_HIP_TRY(g->dist_int.alloc(nt * n * 8, st));
   SSSP_HIP_TRY(g->bitmap.alloc(nt * geo.nwords * 8, st));
   SSSP_HIP_TRY(g->hint.alloc(nt * n * 4, st));
+  SSSP_HIP_TRY(g->tree.alloc(nt * (geo.nwords + (geo.nwords + 63) / 64) * 8, st));
   SSSP_HIP_TRY(g->hubmask.alloc(geo.nwords * 8, st));
   SSSP_HIP_TRY(g->F.alloc((uint64_t)geo.G * geo.segcap * 4, st));
   SSSP_HIP_TRY(g->FD.alloc((uint64_t)geo.G * geo.segcap * 8, st));
@@ -1827,6 +1972,7 @@ sssp_status ensure_workspace(sssp_graph* g, const sssp_tuning& tu, const Geometr
   g->ws_probe_cap = tu.probe_cap;
   g->ws_G = geo.G;
   g->ws_teams = geo.nteams;
+  g->ws_segcap = geo.segcap;
   return SSSP_OK;
 }
 
@@ -1868,6 +2014,10 @@ sssp_status check_params(const sssp_params* params, sssp_params& p, sssp_tuning&
   if (tu.chunk_edges < 64) return fail(SSSP_ERR_INVALID_ARGUMENT, "chunk_edges must be >= 64");
   if (tu.hub_degree > (1u << 22)) return fail(SSSP_ERR_INVALID_ARGUMENT, "hub_degree must be <= 2^22");
   if (tu.sample_cap > tu.probe_cap) return fail(SSSP_ERR_INVALID_ARGUMENT, "sample_cap must be <= probe_cap");
+  if (tu.queue > 1) return fail(SSSP_ERR_INVALID_ARGUMENT, "queue must be 0 (flat array) or 1 (tournament tree)");
+  // Tournament tree: vertices above 64 arcs are relaxed as shared hub chunks
+  // (a workgroup extracts 4096 consecutive, similar-degree vertices).
+  if (tu.queue == 1) tu.hub_degree = std::min(tu.hub_degree, 64u);
   return SSSP_OK;
 }
 
@@ -1920,6 +2070,15 @@ sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uin
   a.max_steps = p.max_steps;
   a.list_threshold = tu.list_divisor == 0xFFFFFFFFu ? 0 : std::max<uint64_t>(1, (uint64_t)g->n / tu.list_divisor);
   a.list_threshold = std::min<uint64_t>(a.list_threshold, geo.lcap);
+  if (tu.queue == 1) {
+    // The tournament tree replaces the explicit list as well as the scan;
+    // local expansion keeps the list's notion of a small queue.
+    a.sparse_q = a.list_threshold;
+    a.list_threshold = 0;
+    a.n2 = (geo.nwords + 63) / 64;
+    a.key1 = (ull*)g->tree.p;
+    a.key2 = a.key1 + (uint64_t)L.nteams * geo.nwords;
+  }
   a.tlimit = g->tick_khz * 1000ull * 20ull;  // 20 s per barrier wait
   a.ns_per_tick = (uint32_t)std::max<uint64_t>(1, 1000000ull / g->tick_khz);
   a.segcap = geo.segcap;

@@ -261,6 +261,68 @@ def test_bidirectional_relaxation(sp):
     assert ei.value.status == 2 and "symmetric" in str(ei.value)
 
 
+TREE = dict(queue=1)  # tournament-tree LaB-PQ (Sec. 4.2, Alg. 2)
+
+
+def test_tournament_tree_queue_parity(sp):
+    """The tournament-tree queue gives the oracle's distances for every rule,
+    with one team or many, and refuses unknown queue kinds."""
+    rng = np.random.default_rng(60)
+    for i in range(50):
+        g = tiny_graph(rng)
+        s = int(rng.integers(0, g.n))
+        exp = ref(g, s)
+        G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+        for rule, kw in RULES:
+            for tun in (TREE, dict(queue=1, teams=8)):
+                dist, _ = sp.solve(G, [s, 0], rule=rule, seed=i, tuning=tun, **kw)
+                assert_same(sp.to_numpy_u64(dist)[0], exp, f"tree, graph {i} n={g.n} {rule} {kw} {tun}")
+                assert_same(sp.to_numpy_u64(dist)[1], ref(g, 0), f"tree, graph {i} source 0 {rule} {kw} {tun}")
+        G.close()
+    for g, rules in [(graphgen.rmat(15, 16, seed=61), [("rho", {"rho": 256}), ("rho", {"rho": 1 << 14}),
+                                                       ("rho_exact", {"rho": 2000}), ("delta", {"delta": 50000}),
+                                                       ("bf", {})]),
+                     (graphgen.road(120, 120, seed=62), [("delta", {"delta": 3000}), ("rho", {"rho": 64}),
+                                                         ("min", {})])]:
+        s = int(np.argmax(g.degrees()))
+        exp = ref(g, s)
+        G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+        for rule, kw in rules:
+            for tun in (TREE, dict(queue=1, hub_degree=16, chunk_edges=64), dict(queue=1, local_budget=64),
+                        dict(queue=1, no_filter=1)):
+                dist, _ = sp.solve(G, [s], rule=rule, tuning=tun, **kw)
+                assert_same(sp.to_numpy_u64(dist)[0], exp, f"tree {rule} {kw} {tun}")
+        G.close()
+    G = sp.Graph.from_csr(*(lambda t: (t.offsets, t.targets, t.weights))(graphgen.grid2d(8, 8, seed=63)))
+    with pytest.raises(sp.SSSPError) as ei:
+        sp.solve(G, [0], tuning=dict(queue=2))
+    assert ei.value.status == 1
+    G.close()
+
+
+def test_tournament_tree_extracts_what_the_flat_array_extracts(sp):
+    """With keys fixed at extraction (repeatable runs), the tree and the flat
+    array are two implementations of one LaB-PQ: every step sees the same
+    threshold, queue size, extracted set size and relaxed arcs."""
+    for g, s, rules in [(graphgen.road(100, 100, seed=64), 5000, [("delta", {"delta": 2500}), ("bf", {}), ("min", {})]),
+                        (graphgen.rmat(13, 8, seed=65), None, [("delta", {"delta": 40000}), ("bf", {})])]:
+        s = int(np.argmax(g.degrees())) if s is None else s
+        G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+        for rule, kw in rules:
+            traces = {}
+            for name, tun in (("flat", None), ("tree", TREE)):
+                dist, st = sp.solve(G, [s], rule=rule, tuning=tun, snapshot_keys=True, trace=1 << 16,
+                                    extract_counts=True, **kw)
+                assert_same(sp.to_numpy_u64(dist)[0], ref(g, s), f"{name} {rule}")
+                traces[name] = ([(r["theta"], r["q"], r["extracted"], r["edges"]) for r in st["trace"]],
+                                st["extract_counts"].cpu().numpy())
+            a, b = traces["flat"][0], traces["tree"][0]
+            first = next((i for i in range(min(len(a), len(b))) if a[i] != b[i]), min(len(a), len(b)))
+            assert a == b, (rule, len(a), len(b), first, a[max(0, first - 1):first + 2], b[max(0, first - 1):first + 2])
+            assert np.array_equal(traces["flat"][1], traces["tree"][1]), rule
+        G.close()
+
+
 def test_exact_rho_selection_on_a_star(sp):
     """With the exact rho-th key (NEXT-4 rule), a star whose leaf weights are
     a permutation of 1..N is settled rho leaves per step: the trace shows
