@@ -611,8 +611,12 @@ constexpr uint32_t HINT_NONE = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint32_t as_hint(ull d) { return d < (ull)HINT_NONE ? (uint32_t)d : HINT_NONE; }
 
-__device__ __forceinline__ bool writemin(uint32_t* hint, ull* dist, int32_t v, ull nd) {
-  if (hint) {
+// check = false skips the filter read (the hint is still kept): in
+// super-sparse steps with local expansion the work is a chain of hops, each
+// waiting for the last, so a read before the atomic costs a round trip per
+// hop and saves little.
+__device__ __forceinline__ bool writemin(uint32_t* hint, ull* dist, int32_t v, ull nd, bool check = true) {
+  if (hint && check) {
     const uint32_t h = (uint32_t)ld_plain(&hint[v]);
     if (h != HINT_NONE && nd >= (ull)h) return false;
   }
@@ -1120,7 +1124,7 @@ __device__ __forceinline__ void relax_batch(const KArgs& a, const Team& tm, ull*
     if (ev[k] == INF) continue;
     ++acc.edges;
     const ull nd = dd[k] + (ev[k] >> 32);
-    if (!writemin(tm.hint, dist, fv[k], nd)) continue;
+    if (!writemin(tm.hint, dist, fv[k], nd, !lx.on)) continue;
     ++acc.succ;
     tree_lower(tm, fv[k], nd);
     // Hubs go to Q, where their arcs are split over the team.
