@@ -120,10 +120,14 @@ typedef struct {
                              steps a workgroup relaxes the vertices its WriteMins bring to
                              at most theta itself, hop after hop, up to this many per step,
                              instead of returning them to Q (default 4096; 0xFFFFFFFF = off;
-                             always off with SSSP_SOLVE_SNAPSHOT_KEYS) */
+                             always off with SSSP_SOLVE_SNAPSHOT_KEYS). Only vertices of
+                             out-degree at most 8 * super_sparse_degree (and at most
+                             hub_degree) are relaxed this way; others go to Q */
   uint32_t super_sparse_degree; /* steps on the explicit list whose previous step relaxed fewer
                              arcs than this per vertex count as super-sparse (default 10;
-                             the first step compares the graph's average out-degree) */
+                             the first step compares the graph's average out-degree); local
+                             expansion runs only on graphs whose average out-degree is below
+                             it */
   uint32_t pull;          /* bidirectional relaxation (Sec. 6): before pushing from u, lower
                              u's key with its neighbours' keys. Needs a graph created with
                              SSSP_UNDIRECTED. 0 = library default (off), 1 = on

@@ -79,16 +79,17 @@ struct sssp_graph {
   uint32_t ws_hub_degree = 0, ws_chunk = 0, ws_probe_cap = 0, ws_G = 0, ws_teams = 0;
   uint64_t ws_src_cap = 0;  // sources the `srcs` buffer holds
   uint64_t ws_segcap = 0;   // F entries per workgroup the workspace was sized for
-  sssp_impl::DevBuf dist_int, bitmap, hint, tree, hubmask, F, FD, H, L, samples, parts, ctl, args, srcs;
+  uint32_t ws_local_cap = 0;  // local-expansion degree cap of bigmask
+  sssp_impl::DevBuf dist_int, bitmap, hint, tree, hubmask, bigmask, F, FD, H, L, samples, parts, ctl, args, srcs;
   void* hargs = nullptr;  // host staging copy of the kernel arguments (operator new)
 
   uint64_t graph_bytes() const { return off.bytes + edges.bytes + perm.bytes + inv.bytes; }
   uint64_t workspace_bytes() const {
-    return dist_int.bytes + bitmap.bytes + hint.bytes + tree.bytes + hubmask.bytes + F.bytes + FD.bytes + H.bytes + L.bytes + samples.bytes +
+    return dist_int.bytes + bitmap.bytes + hint.bytes + tree.bytes + hubmask.bytes + bigmask.bytes + F.bytes + FD.bytes + H.bytes + L.bytes + samples.bytes +
            parts.bytes + ctl.bytes + args.bytes + srcs.bytes;
   }
   void release_ws(hipStream_t st) {
-    for (sssp_impl::DevBuf* b : {&dist_int, &bitmap, &hint, &tree, &hubmask, &F, &FD, &H, &L, &samples, &parts, &ctl, &args, &srcs})
+    for (sssp_impl::DevBuf* b : {&dist_int, &bitmap, &hint, &tree, &hubmask, &bigmask, &F, &FD, &H, &L, &samples, &parts, &ctl, &args, &srcs})
       b->release(st);
     ws_ready = false;
     ws_src_cap = 0;

@@ -166,6 +166,7 @@ struct KArgs {
   const int64_t* off;
   const ull* edges;     // (weight << 32) | target
   const ull* hubmask;   // bit v set iff deg(v) > hub_degree
+  const ull* bigmask;   // bit v set iff deg(v) > the local-expansion degree cap
   const int32_t* perm;  // internal id -> caller id (NULL: identity)
   const int32_t* inv;   // caller id -> internal id (NULL: identity)
   const int32_t* srcs;  // n_src sources, caller ids
@@ -1127,8 +1128,11 @@ __device__ __forceinline__ void relax_batch(const KArgs& a, const Team& tm, ull*
     if (!writemin(tm.hint, dist, fv[k], nd, !lx.on)) continue;
     ++acc.succ;
     tree_lower(tm, fv[k], nd);
-    // Hubs go to Q, where their arcs are split over the team.
-    if (lx.on && nd <= lx.theta && !((ld_plain(&a.hubmask[fv[k] >> 6]) >> (fv[k] & 63)) & 1ull)) {
+    // Vertices above the local degree cap go to Q, where their arcs are
+    // relaxed by the team (local expansion is for small neighbour sets; a
+    // high-degree vertex in one workgroup's list would serialise its arcs
+    // there).
+    if (lx.on && nd <= lx.theta && !((ld_plain(&a.bigmask[fv[k] >> 6]) >> (fv[k] & 63)) & 1ull)) {
       const uint32_t slot = atomicAdd(&sh.lqn[lx.nxt], 1u);
       if (slot < (uint32_t)LQ) {
         sh.lq[lx.nxt][slot] = fv[k];
@@ -1906,6 +1910,12 @@ sssp_tuning resolve_tuning(const sssp_tuning* in) {
   return t;
 }
 
+// Out-degree above which a vertex is not relaxed by local expansion (eight
+// times the super-sparse average degree, at most the hub degree).
+uint32_t local_degree_cap(const sssp_tuning& tu) {
+  return std::min<uint32_t>(tu.hub_degree, 8u * std::min<uint32_t>(tu.super_sparse_degree, 1u << 20));
+}
+
 // Workspace geometry of one solve.
 struct Geometry {
   uint32_t G, nteams, T;
@@ -1947,7 +1957,8 @@ uint64_t control_words(uint32_t nteams) { return (sizeof(GridCtl) + (uint64_t)nt
 
 sssp_status ensure_workspace(sssp_graph* g, const sssp_tuning& tu, const Geometry& geo, hipStream_t st) {
   if (g->ws_ready && g->ws_hub_degree == tu.hub_degree && g->ws_chunk == tu.chunk_edges &&
-      g->ws_probe_cap >= tu.probe_cap && g->ws_G == geo.G && g->ws_teams == geo.nteams && g->ws_segcap == geo.segcap)
+      g->ws_probe_cap >= tu.probe_cap && g->ws_G == geo.G && g->ws_teams == geo.nteams && g->ws_segcap == geo.segcap &&
+      g->ws_local_cap == local_degree_cap(tu))
     return SSSP_OK;
   g->release_ws(st);
   const uint64_t n = (uint64_t)g->n, nt = geo.nteams;
@@ -1956,6 +1967,7 @@ sssp_status ensure_workspace(sssp_graph* g, const sssp_tuning& tu, const Geometr
   SSSP_HIP_TRY(g->hint.alloc(nt * n * 4, st));
   SSSP_HIP_TRY(g->tree.alloc(nt * (geo.nwords + (geo.nwords + 63) / 64) * 8, st));
   SSSP_HIP_TRY(g->hubmask.alloc(geo.nwords * 8, st));
+  SSSP_HIP_TRY(g->bigmask.alloc(geo.nwords * 8, st));
   SSSP_HIP_TRY(g->F.alloc((uint64_t)geo.G * geo.segcap * 4, st));
   SSSP_HIP_TRY(g->FD.alloc((uint64_t)geo.G * geo.segcap * 8, st));
   SSSP_HIP_TRY(g->H.alloc(nt * geo.hcap * 16, st));
@@ -1969,6 +1981,8 @@ sssp_status ensure_workspace(sssp_graph* g, const sssp_tuning& tu, const Geometr
     if (!g->hargs) return fail(SSSP_ERR_OUT_OF_MEMORY, "kernel argument staging");
   }
   hubmask_kernel<<<1024, 256, 0, st>>>((const int64_t*)g->off.p, n, geo.nwords, tu.hub_degree, (ull*)g->hubmask.p);
+  hubmask_kernel<<<1024, 256, 0, st>>>((const int64_t*)g->off.p, n, geo.nwords, local_degree_cap(tu),
+                                       (ull*)g->bigmask.p);
   SSSP_HIP_TRY(hipGetLastError());
   g->ws_ready = true;
   g->ws_hub_degree = tu.hub_degree;
@@ -1977,6 +1991,7 @@ sssp_status ensure_workspace(sssp_graph* g, const sssp_tuning& tu, const Geometr
   g->ws_G = geo.G;
   g->ws_teams = geo.nteams;
   g->ws_segcap = geo.segcap;
+  g->ws_local_cap = local_degree_cap(tu);
   return SSSP_OK;
 }
 
@@ -2052,6 +2067,7 @@ sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uin
   a.off = (const int64_t*)g->off.p;
   a.edges = (const ull*)g->edges.p;
   a.hubmask = (const ull*)g->hubmask.p;
+  a.bigmask = (const ull*)g->bigmask.p;
   a.perm = g->relabelled ? (const int32_t*)g->perm.p : nullptr;
   a.inv = g->relabelled ? (const int32_t*)g->inv.p : nullptr;
   a.dist_out = (ull*)dist;
@@ -2100,6 +2116,10 @@ sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uin
   // Local expansion reads current keys, so snapshot-key runs go without it.
   a.local_budget = (a.snapshot || tu.local_budget == 0xFFFFFFFFu) ? 0u : tu.local_budget;
   a.super_sparse = tu.super_sparse_degree;
+  // Local expansion serves graphs of small degree (the paper's road graphs):
+  // on a graph whose average out-degree is not below the super-sparse
+  // threshold, a step after a low-degree source only looks super-sparse.
+  if ((uint64_t)g->m >= (uint64_t)tu.super_sparse_degree * (uint64_t)g->n) a.local_budget = 0;
   // Bidirectional relaxation reads current keys too; it needs symmetric arcs.
   a.pull = (!a.snapshot && g->undirected && tu.pull != 0xFFFFFFFFu && tu.pull != 0) ? 1u : 0u;
   return SSSP_OK;
