@@ -568,6 +568,13 @@ def test_full_rmat24_rho_sweep(sp, rmat24):
         print(f"rmat24 rho={rho} steps={st['steps']} edges={st['edges_relaxed']} ms={st['device_ms']:.2f}",
               flush=True)
     assert oracle.certificate(g.offsets, g.targets, g.weights, s, got) == (0, -1)
+    # the tournament-tree queue and the stream-ordered call at full size
+    dist, st = sp.solve(G, [s], rule="rho", rho=1 << 16, tuning={"queue": 1})
+    assert_same(sp.to_numpy_u64(dist)[0], exp, "rmat24 tournament tree rho=2^16")
+    print(f"rmat24 tree rho=65536 steps={st['steps']} ms={st['device_ms']:.2f}", flush=True)
+    pending = sp.solve_async(G, [s], rule="rho", rho=1 << 18)
+    dist, _ = pending.wait()
+    assert_same(sp.to_numpy_u64(dist)[0], exp, "rmat24 asynchronous solve")
     # second source: certificate only (linear time)
     s2 = int(rmat24.sources[1])
     dist, _ = sp.solve(G, [s2], rule="rho", rho=1 << 20)
