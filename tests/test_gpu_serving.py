@@ -73,13 +73,15 @@ def test_row_hash_matches_definition(sp, torch_cuda):
         assert sp.row_hash(t) == np_row_hash(d), n
 
 
-@pytest.mark.parametrize("case", ["rmat", "road"])
+@pytest.mark.parametrize("case", ["rmat", "road", "rmat-tree"])
 def test_server_matches_oracle(sp, torch_cuda, side_stream, case):
     torch = torch_cuda
-    if case == "rmat":
+    if case.startswith("rmat"):
         g = graphgen.rmat(13, 16, seed=41)
         G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
         kw = dict(rule="rho", rho=2048)
+        if case == "rmat-tree":
+            kw["tuning"] = {"queue": 1}  # tournament-tree LaB-PQ (Sec. 4.2)
     else:
         g = graphgen.road(70, 70, seed=42)
         G = sp.Graph.from_csr(g.offsets, g.targets, g.weights, reorder=False)
