@@ -638,19 +638,24 @@ __device__ __forceinline__ bool mark(ull* bitmap, int32_t v) {
 // below a node relaxes what it extracted, and vertices are numbered by
 // decreasing degree, so in this mode every vertex above 64 arcs is relaxed
 // through the team's shared hub chunks instead (the launch lowers
-// hub_degree to 64), which keeps Relax balanced. Alg. 2's Mark sets "renewed" flags up the path and Update
-// recomputes those nodes before the next Extract; here the keys that Relax
-// can only lower are lowered at once with an atomic min (Mark's walk up,
-// which stops where a node already holds a smaller key, as Alg. 2's stops at
-// a flag already set), and the nodes that Extract raises are recomputed by
+// hub_degree to 64), which keeps Relax balanced.
+//
+// Alg. 2's Mark flags the nodes on the path to the root as changed, and its
+// Update recomputes the flagged nodes before the next Extract. Here the keys
+// that Relax can only lower are lowered at once with an atomic min (the walk
+// up stops where a node already holds a smaller key, as Alg. 2's stops at a
+// node already flagged), and the nodes that Extract raises are recomputed by
 // the workgroup that owns them during that Extract. A node may hold less than
 // the minimum below it (a lowered key whose vertex was not queued); Extract
 // then finds nothing there and sets the node exact. It never holds more, so
-// descending only into nodes with key <= theta finds every such vertex. A
-// plain read first skips the atomic when the node already holds a key <= d
-// (most WriteMins: the node is the minimum of 64 keys, and many WriteMins
-// land on the same few words, where atomics would serialise); a stale read
-// is never smaller than the node's key, so no lowering is lost.
+// descending only into nodes with key <= theta finds every such vertex.
+//
+// A plain read first skips the atomic when the node already holds a key
+// <= d (most WriteMins: the node is the minimum of 64 keys, and many
+// WriteMins land on the same few words, where atomics would serialise).
+// Within Relax the nodes only fall and the per-CU cache was invalidated at
+// the phase's barrier, so a stale read is never below the node's key and no
+// lowering is lost.
 __device__ __forceinline__ void tree_lower(const Team& tm, int32_t v, ull d) {
   if (!tm.key1) return;
   ull* k1 = &tm.key1[v >> 6];
