@@ -141,7 +141,9 @@ typedef struct {
                              atomic min on every successful WriteMin (Mark, stopping where a
                              node already holds a smaller key) and recomputed by the workgroup
                              that extracts below it; Extract descends only into nodes whose key
-                             is at most theta. Same extracted sets, so the same distances */
+                             is at most theta. Same extracted sets, so the same distances.
+                             In this mode hub_degree is capped at 64 (a workgroup extracts
+                             4096 consecutive vertices, so larger rows are shared instead) */
   uint32_t reserved2;
 } sssp_tuning;
 
