@@ -64,7 +64,8 @@ typedef enum {
    * estimated from s = ceil(10 * (q / rho + log q)) uniform samples of the
    * queue, log q = 1 + log2(q + 1), taking the ceil(rho * s / q)-th smallest
    * (App. B, c = 10). If q <= rho the whole queue is extracted. The first two
-   * steps that scan the bitmap use floor(rho / 10) instead of rho (Sec. 6). */
+   * steps whose queue holds more than floor(rho / 10) vertices use
+   * floor(rho / 10) instead of rho (Sec. 6). */
   SSSP_RULE_RHO = 0,
   /* Delta*-stepping (Table 2, Thm. 5.5): theta = i * Delta, i = 1, 2, ...
    * advancing every step, skipping ahead to ceil(min key / Delta) when the

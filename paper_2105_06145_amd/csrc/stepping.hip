@@ -1725,7 +1725,7 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
       ph0 += lap();
     }
 
-    ull q = 1, minq = 0, idelta = 0, dense_steps = 0;
+    ull q = 1, minq = 0, idelta = 0, large_steps = 0;
     // Vertices relaxed and arcs of the previous step (before the first: the
     // whole graph, so that the first step is super-sparse when the graph is).
     ull prev_x = n, prev_e = a.m;
@@ -1783,9 +1783,12 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
           ph1 += lap();
         }
       } else {
-        // The first two bitmap steps use rho / 10 (Sec. 6).
-        const ull rho_eff = (dense && dense_steps < 2) ? ((a.rho / 10) > 0 ? a.rho / 10 : 1) : a.rho;
-        if (dense) ++dense_steps;
+        // The first two steps whose queue exceeds rho / 10 use rho / 10 (Sec. 6
+        // lowers rho for the first large steps, whose threshold estimates are
+        // the least accurate).
+        const ull rho10 = (a.rho / 10) > 0 ? a.rho / 10 : 1;
+        const ull rho_eff = large_steps < 2 ? rho10 : a.rho;
+        if (q > rho10) ++large_steps;
         if (q > rho_eff) {
           sampled = true;
           const ull probes = rho_probes(q, rho_eff, n, dense, a.sample_cap, a.probe_cap);

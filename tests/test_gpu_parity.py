@@ -152,11 +152,12 @@ def test_rho_small_queue_extracts_everything(sp):
         assert_same(sp.to_numpy_u64(dist)[0], exp, f"rho {rho}")
         recs = st["trace"]
         assert len(recs) == st["steps"]
-        dense_seen = 0
+        large_seen = 0  # steps whose queue exceeded rho / 10: the first two use rho / 10
         for r in recs:
-            rho_eff = max(1, rho // 10) if (r["flags"] & 1) and dense_seen < 2 else rho
-            if r["flags"] & 1:
-                dense_seen += 1
+            rho10 = max(1, rho // 10)
+            rho_eff = rho10 if large_seen < 2 else rho
+            if r["q"] > rho10:
+                large_seen += 1
             if r["q"] <= rho_eff:
                 assert r["extracted"] == r["q"] and not (r["flags"] & 4)
             else:
