@@ -14,10 +14,11 @@
 //                plus, while |Q| is small, an explicit list (Sec. 6, sparse
 //                mode), so small steps do not scan all n flags.
 //   S3 Relax     for u in F, v in N(u): WriteMin(delta[v], delta[u] + w) as a
-//                64-bit atomic min (Sec. 2 WriteMin), skipped when a plain read
-//                of delta[v] already shows no improvement. delta[u] is read
-//                when u's arcs are relaxed, so a u whose key another WriteMin
-//                of the same step has lowered already propagates the lower key.
+//                64-bit atomic min (Sec. 2 WriteMin), skipped when a 32-bit
+//                upper bound of delta[v] (hint[v]) already shows no
+//                improvement. delta[u] is read when u's arcs are relaxed,
+//                so a u whose key another WriteMin of the same step has
+//                lowered already propagates the lower key.
 //                With SSSP_SOLVE_SNAPSHOT_KEYS, delta[u] is instead the key u
 //                was extracted with (kept beside u in F): what a step extracts
 //                and which vertices it improves then do not depend on the order
@@ -272,6 +273,18 @@ __shared__ Team g_tm;
 // ---------------------------------------------------------------------------
 // Small device helpers.
 
+// Global-address-space view of a device pointer. Loads, stores and atomics
+// through it compile to global_* instructions, which count only against the
+// vector-memory counter; flat_* instructions (what a generic pointer gives)
+// count against the LDS counter too, so every wait for an LDS read would also
+// wait for every gather in flight. For device buffers only, never LDS.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> glob(T* p) {
+  return (gptr<T>)p;
+}
+
 // Plain load: may hit the per-CU L1. Used for immutable data and for the
 // Relax filter, where a stale (never smaller) key is harmless.
 template <class P>
@@ -286,7 +299,7 @@ __device__ __forceinline__ ull ld_agent(P p) {
 // Streaming load for the arc array: each arc is read once per relaxation
 // pass, so it is marked non-temporal and does not push the keys of
 // frequently relaxed targets out of L2.
-__device__ __forceinline__ ull ld_stream(const ull* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ ull ld_stream(const ull* p) { return __builtin_nontemporal_load(glob(p)); }
 template <class P>
 __device__ __forceinline__ int32_t ld_agent_i32(P p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -602,9 +615,8 @@ __device__ __noinline__ void wave_push_hubs(const KArgs& a, ull* H, StepSlot* S,
   }
 }
 
-// WriteMin(delta[v], nd) (S3). Returns true when it lowered delta[v].
-// Filter: hint[v] is a 32-bit upper bound of delta[v] (HINT_NONE: none
-// known), kept by the successful WriteMins with plain stores; a stale hint is
+// WriteMin filter (S3): hint[v] is a 32-bit upper bound of delta[v]
+// (HINT_NONE: none known), kept by the successful WriteMins with plain stores; a stale hint is
 // still an upper bound, since keys only fall. nd >= hint[v] means the WriteMin
 // cannot succeed, so the atomic is skipped. The hints take half the cache
 // lines of the keys, and this read is the one random read of every arc.
@@ -616,20 +628,11 @@ __device__ __forceinline__ uint32_t as_hint(ull d) { return d < (ull)HINT_NONE ?
 // super-sparse steps with local expansion the work is a chain of hops, each
 // waiting for the last, so a read before the atomic costs a round trip per
 // hop and saves little.
-__device__ __forceinline__ bool writemin(uint32_t* hint, ull* dist, int32_t v, ull nd, bool check = true) {
-  if (hint && check) {
-    const uint32_t h = (uint32_t)ld_plain(&hint[v]);
-    if (h != HINT_NONE && nd >= (ull)h) return false;
-  }
-  if (!(nd < atom_min(&dist[v], nd))) return false;
-  if (hint) hint[v] = as_hint(nd);
-  return true;
-}
 
 // Update(v) (S4): set v's flag; true when v is new to Q.
 __device__ __forceinline__ bool mark(ull* bitmap, int32_t v) {
   const ull bit = 1ull << (v & 63);
-  return !(atom_or(&bitmap[v >> 6], bit) & bit);
+  return !(__hip_atomic_fetch_or(glob(&bitmap[v >> 6]), bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit);
 }
 
 // Tournament-tree queue (Sec. 4.2, Alg. 2), fan-out 64: node key1[w] holds
@@ -1123,33 +1126,79 @@ __device__ __forceinline__ void relax_batch(const KArgs& a, const Team& tm, ull*
                                             const ull (&dd)[UNROLL]) {
   Shared& sh = g_sh;
   int32_t fv[UNROLL];
+  uint32_t hv[UNROLL];
   unsigned mask = 0;
+  // The batch's key-bound reads first, all in flight together: no branch
+  // around a read (an absent arc reads hint[0]), and a wave-uniform switch,
+  // because a load under a divergent branch makes the compiler wait for
+  // every load in flight where the branch rejoins. Local expansion skips the
+  // filter: its vertices' keys were lowered within this step.
+  const bool filter = __builtin_amdgcn_readfirstlane((tm.hint != nullptr && !lx.on) ? 1 : 0) != 0;
 #pragma unroll
   for (int k = 0; k < UNROLL; ++k) {
     fv[k] = (int32_t)(uint32_t)ev[k];
+    hv[k] = HINT_NONE;
+  }
+  if (filter) {
+    const gptr<uint32_t> hint = glob(tm.hint);
+#pragma unroll
+    for (int k = 0; k < UNROLL; ++k)
+      hv[k] = __hip_atomic_load(&hint[ev[k] == INF ? 0 : fv[k]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  // WriteMin (S3) of every arc that passes the filter, all atomics issued
+  // before the first result is used; then the successes.
+  ull nd[UNROLL], old[UNROLL];
+  unsigned pass = 0;
+#pragma unroll
+  for (int k = 0; k < UNROLL; ++k) {
+    nd[k] = dd[k] + (ev[k] >> 32);
+    old[k] = 0;
     if (ev[k] == INF) continue;
     ++acc.edges;
-    const ull nd = dd[k] + (ev[k] >> 32);
-    if (!writemin(tm.hint, dist, fv[k], nd, !lx.on)) continue;
+    if (hv[k] == HINT_NONE || nd[k] < (ull)hv[k]) pass |= 1u << k;
+  }
+  const gptr<ull> gdist = glob(dist);
+#pragma unroll
+  for (int k = 0; k < UNROLL; ++k)
+    if ((pass >> k) & 1u)
+      old[k] = __hip_atomic_fetch_min(&gdist[fv[k]], nd[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned upd = 0;  // successes that go to Q
+#pragma unroll
+  for (int k = 0; k < UNROLL; ++k) {
+    if (!((pass >> k) & 1u) || !(nd[k] < old[k])) continue;
+    if (tm.hint) *glob(&tm.hint[fv[k]]) = as_hint(nd[k]);
     ++acc.succ;
-    tree_lower(tm, fv[k], nd);
+    tree_lower(tm, fv[k], nd[k]);
     // Vertices above the local degree cap go to Q, where their arcs are
     // relaxed by the team (local expansion is for small neighbour sets; a
     // high-degree vertex in one workgroup's list would serialise its arcs
     // there).
-    if (lx.on && nd <= lx.theta && !((ld_plain(&a.bigmask[fv[k] >> 6]) >> (fv[k] & 63)) & 1ull)) {
+    if (lx.on && nd[k] <= lx.theta && !((ld_plain(&a.bigmask[fv[k] >> 6]) >> (fv[k] & 63)) & 1ull)) {
       const uint32_t slot = atomicAdd(&sh.lqn[lx.nxt], 1u);
       if (slot < (uint32_t)LQ) {
         sh.lq[lx.nxt][slot] = fv[k];
         continue;
       }
     }
-    acc.minnew = umin(acc.minnew, nd);
-    if (mark(tm.bitmap, fv[k])) {
+    acc.minnew = umin(acc.minnew, nd[k]);
+    upd |= 1u << k;
+  }
+  // Update (S4): set the flags, again all atomics before the first result.
+  ull ow[UNROLL];
+  const gptr<ull> gbits = glob(tm.bitmap);
+#pragma unroll
+  for (int k = 0; k < UNROLL; ++k) {
+    ow[k] = 0;
+    if ((upd >> k) & 1u)
+      ow[k] = __hip_atomic_fetch_or(&gbits[fv[k] >> 6], 1ull << (fv[k] & 63), __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+  }
+#pragma unroll
+  for (int k = 0; k < UNROLL; ++k)
+    if (((upd >> k) & 1u) && !((ow[k] >> (fv[k] & 63)) & 1ull)) {
       ++acc.fresh;
       mask |= 1u << k;
     }
-  }
   if (emit) list_append(a, S, Lnext, fv, mask);
 }
 
@@ -1164,8 +1213,8 @@ __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* 
   uint32_t deg = 0;
   ull rb = 0;
   if (u >= 0) {
-    rb = (ull)a.off[u];
-    deg = (uint32_t)((ull)a.off[u + 1] - rb);
+    rb = (ull)*glob(&a.off[u]);
+    deg = (uint32_t)((ull)*glob(&a.off[u + 1]) - rb);
   }
   uint32_t total;
   const uint32_t excl = wg_scan(sh, deg, total);
@@ -1206,21 +1255,22 @@ __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* 
     }
     __syncthreads();
   }
+  const ull* edges = a.edges;
   for (uint32_t e0 = 0; e0 < total; e0 += WG * UNROLL) {
     ull ev[UNROLL], dd[UNROLL];
 #pragma unroll
     for (int k = 0; k < UNROLL; ++k) {
+      // Lanes past the tile's end read its last arc and drop it: the reads
+      // stay unconditional, so the batch's reads are in flight together.
       const uint32_t e = e0 + k * WG + tid;
-      ev[k] = INF;
-      dd[k] = 0;
-      if (e < total) {
-        int lo = 0;
+      const uint32_t ec = e < total ? e : total - 1;
+      int lo = 0;
 #pragma unroll
-        for (int step = WG / 2; step > 0; step >>= 1)
-          if (sh.pre[lo + step] <= e) lo += step;
-        ev[k] = ld_stream(&a.edges[sh.beg[lo] + (e - sh.pre[lo])]);
-        dd[k] = sh.du[lo];
-      }
+      for (int step = WG / 2; step > 0; step >>= 1)
+        if (sh.pre[lo + step] <= ec) lo += step;
+      const ull arc = ld_stream(&edges[sh.beg[lo] + (ec - sh.pre[lo])]);
+      ev[k] = e < total ? arc : INF;
+      dd[k] = sh.du[lo];
     }
     relax_batch(a, tm, dist, S, Lnext, emit, acc, lx, ev, dd);
   }
@@ -1278,12 +1328,16 @@ __device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S,
         du = best;
       }
     }
+    const ull* edges = a.edges;
     for (ull e0 = beg; e0 < end; e0 += (ull)WG * UNROLL) {
       ull ev[UNROLL], dd[UNROLL];
 #pragma unroll
       for (int k = 0; k < UNROLL; ++k) {
+        // A chunk is never empty; lanes past its end read its last arc and
+        // drop it (unconditional reads, in flight together).
         const ull e = e0 + (ull)k * WG + tid;
-        ev[k] = e < end ? ld_stream(&a.edges[e]) : INF;
+        const ull arc = ld_stream(&edges[e < end ? e : end - 1]);
+        ev[k] = e < end ? arc : INF;
         dd[k] = du;
       }
       relax_batch(a, tm, dist, S, Lnext, emit, acc, lx, ev, dd);
