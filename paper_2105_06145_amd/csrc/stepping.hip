@@ -836,41 +836,99 @@ __device__ __noinline__ ExtractOut phase_extract_dense(const KArgs& a, const ull
   return o;
 }
 
-// S2, bitmap step without an explicit list to build. Each lane owns words as
-// above and walks its members with no workgroup barrier, reserving F slots
-// with an LDS counter; rounds are wave-uniform so that extracted hubs are
-// recorded with one atomic per wave.
+// Position of the n-th (from 0) set bit of w, by halving with popcounts.
+__device__ __forceinline__ int select_bit(ull w, uint32_t n) {
+  int pos = 0;
+#pragma unroll
+  for (int h = 32; h > 0; h >>= 1) {
+    const uint32_t c = (uint32_t)__popcll(w & ((1ull << h) - 1ull));
+    if (n >= c) {
+      n -= c;
+      w >>= h;
+      pos += h;
+    }
+  }
+  return pos;
+}
+
+// S2, bitmap step without an explicit list to build. Each thread loads one
+// owned word per round (the block layout above); the round's members are
+// then dealt out evenly: a prefix sum of the words' member counts in LDS, and
+// thread j takes members j, j + WG, ... (its word by binary search, its bit by
+// rank), so a round costs the workgroup's member count over WG key reads per
+// lane rather than the fullest word's (a lane walking a word of 64 members
+// made the whole wave wait for 16 dependent reads). Consecutive threads take
+// consecutive members, so the key reads coalesce where words are crowded.
+// Extracted bits are collected per word with LDS atomics and written back by
+// the word's owner; F slots come from an LDS counter, hubs are recorded with
+// one atomic per wave.
 __device__ __noinline__ ExtractOut phase_extract_dense_fast(const KArgs& a, const ull* dist, StepSlot* S,
                                                             ull theta) {
   const Team& tm = g_tm;
   Shared& sh = g_sh;
+  const unsigned tid = threadIdx.x;
   const ull nw = a.nwords, T = tm.T;
   const ull nblocks = (nw + BLOCK_WORDS - 1) / BLOCK_WORDS;
   constexpr ull BLOCKS_PER_ROUND = WG / BLOCK_WORDS;
   ExtractOut o{0, 0, INF};
-  if (threadIdx.x == 0) sh.fcnt = 0;
+  if (tid == 0) sh.fcnt = 0;
   __syncthreads();
   uint32_t* xc = a.xcount ? a.xcount + ld_agent(&tm.ctl->query) * (ull)a.n : nullptr;
+  // Arguments in registers and global-address-space pointers: a store
+  // through a generic pointer might alias the argument block, and the
+  // compiler would re-read (and wait for) the arguments after every F store.
+  const ull segcap = a.segcap;
+  const bool snap = a.snapshot;
+  const int32_t* perm = a.perm;
+  const gptr<int32_t> Fb = glob(tm.Fb);
+  const gptr<ull> FDb = glob(tm.FDb);
+  const gptr<ull> bits = glob(tm.bitmap);
+  const gptr<const ull> hubmask = glob(a.hubmask);
+  const gptr<const ull> gd = glob(dist);
+  // The Relax tile arrays are free during Extract: the round's words, their
+  // hub flags and the bits extracted from them.
+  ull* const wword = sh.beg;
+  ull* const whub = sh.du;
+  ull* const wclear = sh.pulled;
   for (ull r0 = tm.rank; r0 < nblocks; r0 += T * BLOCKS_PER_ROUND) {
-    const ull blk = r0 + T * (threadIdx.x / BLOCK_WORDS);
-    const ull wi = blk * BLOCK_WORDS + (threadIdx.x % BLOCK_WORDS);
-    const ull word = (blk < nblocks && wi < nw) ? ld_agent(&tm.bitmap[wi]) : 0ull;
-    const ull hubw = word ? ld_plain(&a.hubmask[wi]) : 0ull;
-    ull rest = word, clear = 0;
-    while (__ballot(rest != 0)) {
+    const ull blk = r0 + T * (tid / BLOCK_WORDS);
+    const ull wi = blk * BLOCK_WORDS + (tid % BLOCK_WORDS);
+    const ull word =
+        (blk < nblocks && wi < nw) ? __hip_atomic_load(&bits[wi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+    const ull hubw = word ? hubmask[wi] : 0ull;
+    uint32_t total;
+    const uint32_t excl = wg_scan(sh, (uint32_t)__popcll(word), total);
+    sh.pre[tid] = excl;
+    wword[tid] = word;
+    whub[tid] = hubw;
+    wclear[tid] = 0;
+    __syncthreads();
+    for (uint32_t j0 = 0; j0 < total; j0 += WG * BATCH) {
       int32_t v[BATCH];
+      int own[BATCH];
       ull d[BATCH];
 #pragma unroll
       for (int k = 0; k < BATCH; ++k) {
+        const uint32_t j = j0 + k * WG + tid;
         v[k] = -1;
-        if (rest) {
-          const int bit = __ffsll((long long)rest) - 1;
-          rest &= rest - 1;
-          v[k] = (int32_t)(wi * 64 + bit);
+        own[k] = 0;
+        if (j < total) {
+          int lo = 0;
+#pragma unroll
+          for (int step = WG / 2; step > 0; step >>= 1)
+            if (sh.pre[lo + step] <= j) lo += step;
+          const int bit = select_bit(wword[lo], j - sh.pre[lo]);
+          const ull owi = (r0 + T * (ull)(lo / BLOCK_WORDS)) * BLOCK_WORDS + (ull)(lo % BLOCK_WORDS);
+          v[k] = (int32_t)(owi * 64 + (ull)bit);
+          own[k] = lo;
         }
       }
 #pragma unroll
-      for (int k = 0; k < BATCH; ++k) d[k] = v[k] >= 0 ? ld_agent(&dist[v[k]]) : INF;
+      for (int k = 0; k < BATCH; ++k) {
+        // Unconditional reads (vertex 0 for an empty slot): in flight together.
+        d[k] = __hip_atomic_load(&gd[v[k] >= 0 ? v[k] : 0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v[k] < 0) d[k] = INF;
+      }
       unsigned hub_taken = 0;
 #pragma unroll
       for (int k = 0; k < BATCH; ++k) {
@@ -878,22 +936,22 @@ __device__ __noinline__ ExtractOut phase_extract_dense_fast(const KArgs& a, cons
         const ull bit = 1ull << (v[k] & 63);
         bool ext = d[k] <= theta;
         if (ext) {
-          if ((hubw & bit) != 0) {
+          if ((whub[own[k]] & bit) != 0) {
             hub_taken |= 1u << k;
           } else {
             const uint32_t slot = atomicAdd(&sh.fcnt, 1u);
-            if (slot < a.segcap) {
-              tm.Fb[slot] = v[k];
-              if (a.snapshot) tm.FDb[slot] = d[k];
+            if (slot < segcap) {
+              Fb[slot] = v[k];
+              if (snap) FDb[slot] = d[k];
             } else {
               ext = false;  // no room: stays queued
             }
           }
         }
         if (ext) {
-          clear |= bit;
+          atomicOr(&wclear[own[k]], bit);
           ++o.x;
-          if (xc) xc[a.perm ? a.perm[v[k]] : v[k]] += 1u;
+          if (xc) xc[perm ? perm[v[k]] : v[k]] += 1u;
         } else {
           o.minkept = umin(o.minkept, d[k]);
         }
@@ -903,10 +961,12 @@ __device__ __noinline__ ExtractOut phase_extract_dense_fast(const KArgs& a, cons
         for (int k = 0; k < BATCH; ++k) wave_push_hubs(a, tm.H, S, (hub_taken >> k) & 1u, v[k], d[k]);
       }
     }
-    if (clear) tm.bitmap[wi] = word & ~clear;  // this lane owns word wi
+    __syncthreads();
+    const ull clear = wclear[tid];
+    if (clear) bits[wi] = word & ~clear;  // this thread owns word wi
+    __syncthreads();  // the LDS arrays are refilled next round
   }
-  __syncthreads();
-  o.fcnt = (uint32_t)umin((ull)sh.fcnt, a.segcap);
+  o.fcnt = (uint32_t)umin((ull)sh.fcnt, segcap);
   return o;
 }
 
@@ -931,18 +991,33 @@ __device__ __noinline__ ExtractOut phase_extract_dense_words(const KArgs& a, con
   if (threadIdx.x == 0) sh.fcnt = 0;
   __syncthreads();
   uint32_t* xc = a.xcount ? a.xcount + ld_agent(&tm.ctl->query) * (ull)a.n : nullptr;
+  // As in the lane walk: arguments in registers, global-address-space
+  // pointers, and unconditional reads.
+  const ull segcap = a.segcap;
+  const bool snap = a.snapshot;
+  const int32_t* perm = a.perm;
+  const gptr<int32_t> Fb = glob(tm.Fb);
+  const gptr<ull> FDb = glob(tm.FDb);
+  const gptr<ull> bits = glob(tm.bitmap);
+  const gptr<const ull> hubmask = glob(a.hubmask);
+  const gptr<const ull> gd = glob(dist);
   for (ull blk0 = tm.rank; blk0 < nblocks; blk0 += (ull)WPI * T) {
     ull wi[WPI], word[WPI], d[WPI], hubw[WPI];
 #pragma unroll
     for (int k = 0; k < WPI; ++k) {
       const ull blk = blk0 + (ull)k * T;
       wi[k] = blk * BLOCK_WORDS + wave;
-      word[k] = (blk < nblocks && wi[k] < nw) ? ld_agent(&tm.bitmap[wi[k]]) : 0ull;
+      const bool in = blk < nblocks && wi[k] < nw;
+      word[k] = __hip_atomic_load(&bits[in ? wi[k] : 0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (!in) word[k] = 0;
     }
 #pragma unroll
     for (int k = 0; k < WPI; ++k) {
-      d[k] = ((word[k] >> lane) & 1ull) ? ld_agent(&dist[wi[k] * 64 + lane]) : INF;
-      hubw[k] = word[k] ? ld_plain(&a.hubmask[wi[k]]) : 0ull;
+      const bool member = (word[k] >> lane) & 1ull;
+      d[k] = __hip_atomic_load(&gd[member ? wi[k] * 64 + lane : 0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (!member) d[k] = INF;
+      hubw[k] = hubmask[word[k] ? wi[k] : 0];
+      if (!word[k]) hubw[k] = 0;
     }
 #pragma unroll
     for (int k = 0; k < WPI; ++k) {
@@ -958,9 +1033,9 @@ __device__ __noinline__ ExtractOut phase_extract_dense_words(const KArgs& a, con
         base = __shfl(base, 0);
         if (ext && !hub) {
           const uint32_t slot = base + (uint32_t)__popcll(want & below_lane);
-          if (slot < a.segcap) {
-            tm.Fb[slot] = v;
-            if (a.snapshot) tm.FDb[slot] = d[k];
+          if (slot < segcap) {
+            Fb[slot] = v;
+            if (snap) FDb[slot] = d[k];
           } else {
             ext = false;  // no room: stays queued
           }
@@ -969,16 +1044,16 @@ __device__ __noinline__ ExtractOut phase_extract_dense_words(const KArgs& a, con
       wave_push_hubs(a, tm.H, S, ext && hub, v, d[k]);
       if (ext) {
         ++o.x;
-        if (xc) xc[a.perm ? a.perm[v] : v] += 1u;
+        if (xc) xc[perm ? perm[v] : v] += 1u;
       } else if (member) {
         o.minkept = umin(o.minkept, d[k]);
       }
       const ull taken = __ballot(ext);
-      if (taken && lane == 0) tm.bitmap[wi[k]] = word[k] & ~taken;  // this wave owns word wi
+      if (taken && lane == 0) bits[wi[k]] = word[k] & ~taken;  // this wave owns word wi
     }
   }
   __syncthreads();
-  o.fcnt = (uint32_t)umin((ull)sh.fcnt, a.segcap);
+  o.fcnt = (uint32_t)umin((ull)sh.fcnt, segcap);
   return o;
 }
 
