@@ -356,6 +356,39 @@ def test_exact_rho_selection_on_a_star(sp):
     G.close()
 
 
+def test_crowded_bitmap_words_extract_each_member_once(sp):
+    """Bitmap Extract below n/4 queued deals a round's members out over the
+    workgroup. A star whose leaves fill 768 consecutive bitmap words (plus a
+    word of 37 members and 3,000 words of one member) puts thousands of
+    members in one workgroup's round when teams are small; every leaf's key
+    is final when it is queued, so each leaf must be extracted exactly once
+    whatever the threshold splits (a bit cleared by mistake leaves it never
+    extracted, a bit left set extracts it twice)."""
+    n = 1 << 18
+    rng = np.random.default_rng(31)
+    full = np.arange(0, 768 * 64)
+    ragged = np.arange(768 * 64, 768 * 64 + 37)
+    singles = (np.arange(1000, 4000) * 64 + rng.integers(0, 64, 3000))
+    leaves = np.concatenate([full, ragged, singles])
+    src = n - 1
+    w = rng.permutation(leaves.size) + 1
+    g = graphgen.from_arcs(n, np.full(leaves.size, src, dtype=np.int64), leaves, w)
+    exp = ref(g, src)
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights, reorder=False)
+    tun = dict(NO_LOCAL, blocks_per_cu=1, teams=16)
+    dense_lane_steps = 0
+    for rule, kw in [("rho", {"rho": 2000}), ("rho", {"rho": 40000}), ("rho_exact", {"rho": 5000}),
+                     ("delta", {"delta": 9000}), ("bf", {}), ("min", {})]:
+        dist, st = sp.solve(G, [src], rule=rule, tuning=tun, trace=1 << 16, extract_counts=True, **kw)
+        assert_same(sp.to_numpy_u64(dist)[0], exp, f"crowded {rule} {kw}")
+        xc = st["extract_counts"].cpu().numpy()[0]
+        assert xc[src] == 1 and np.all(xc[leaves] == 1), (rule, kw, int(xc[leaves].min()), int(xc[leaves].max()))
+        assert int(xc.sum()) == leaves.size + 1, (rule, kw)
+        dense_lane_steps += sum(1 for r in st["trace"] if (r["flags"] & 1) and n // 64 < r["q"] < n // 4)
+    assert dense_lane_steps > 0
+    G.close()
+
+
 def test_seeds_and_repeats_agree(sp):
     g = graphgen.rmat(14, 16, seed=15)
     s = int(np.argmax(g.degrees()))
