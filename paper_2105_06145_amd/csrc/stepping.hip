@@ -1280,7 +1280,10 @@ __device__ __forceinline__ void relax_batch(const KArgs& a, const Team& tm, ull*
 // Relax the arcs of up to WG vertices (one per thread; u < 0 for none, du its
 // key) as one tile: degree prefix sums and row starts in LDS, then UNROLL
 // arcs per lane per round, consecutive lanes on consecutive arcs. Whole
-// workgroup, uniform call.
+// workgroup, uniform call. Sparse: the graph's tiles hold few arcs (local
+// expansion is on), so lanes past the tile's end skip their reads rather
+// than repeat the last arc's.
+template <bool Sparse>
 __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* dist, StepSlot* S, int32_t* Lnext,
                                            bool emit, RelaxAcc& acc, const Local& lx, int32_t u, ull du) {
   Shared& sh = g_sh;
@@ -1335,17 +1338,30 @@ __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* 
     ull ev[UNROLL], dd[UNROLL];
 #pragma unroll
     for (int k = 0; k < UNROLL; ++k) {
-      // Lanes past the tile's end read its last arc and drop it: the reads
-      // stay unconditional, so the batch's reads are in flight together.
       const uint32_t e = e0 + k * WG + tid;
-      const uint32_t ec = e < total ? e : total - 1;
-      int lo = 0;
+      if constexpr (Sparse) {
+        ev[k] = INF;
+        dd[k] = 0;
+        if (e < total) {
+          int lo = 0;
 #pragma unroll
-      for (int step = WG / 2; step > 0; step >>= 1)
-        if (sh.pre[lo + step] <= ec) lo += step;
-      const ull arc = ld_stream(&edges[sh.beg[lo] + (ec - sh.pre[lo])]);
-      ev[k] = e < total ? arc : INF;
-      dd[k] = sh.du[lo];
+          for (int step = WG / 2; step > 0; step >>= 1)
+            if (sh.pre[lo + step] <= e) lo += step;
+          ev[k] = ld_stream(&edges[sh.beg[lo] + (e - sh.pre[lo])]);
+          dd[k] = sh.du[lo];
+        }
+      } else {
+        // Lanes past the tile's end read its last arc and drop it: the reads
+        // stay unconditional, so the batch's reads are in flight together.
+        const uint32_t ec = e < total ? e : total - 1;
+        int lo = 0;
+#pragma unroll
+        for (int step = WG / 2; step > 0; step >>= 1)
+          if (sh.pre[lo + step] <= ec) lo += step;
+        const ull arc = ld_stream(&edges[sh.beg[lo] + (ec - sh.pre[lo])]);
+        ev[k] = e < total ? arc : INF;
+        dd[k] = sh.du[lo];
+      }
     }
     relax_batch(a, tm, dist, S, Lnext, emit, acc, lx, ev, dd);
   }
@@ -1423,6 +1439,7 @@ __device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S,
   // (capped at LQ; pushes beyond it went to Q).
   uint32_t cnt = ex.fcnt, cur = 1;
   ull done_local = 0;
+  const bool sparse_graph = __builtin_amdgcn_readfirstlane(a.local_budget > 0 ? 1 : 0) != 0;
   for (bool first = true;; first = false) {
     for (uint32_t j0 = 0; j0 < cnt; j0 += WG) {
       const uint32_t j = j0 + tid;
@@ -1432,7 +1449,10 @@ __device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S,
         u = first ? tm.Fb[j] : sh.lq[cur][j];
         du = (first && a.snapshot) ? tm.FDb[j] : ld_agent(&dist[u]);
       }
-      relax_tile(a, tm, dist, S, Lnext, emit, acc, lx, u, du);
+      if (sparse_graph)
+        relax_tile<true>(a, tm, dist, S, Lnext, emit, acc, lx, u, du);
+      else
+        relax_tile<false>(a, tm, dist, S, Lnext, emit, acc, lx, u, du);
     }
     if (!local) break;
     cur = lx.nxt;
