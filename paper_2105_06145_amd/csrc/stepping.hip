@@ -616,9 +616,9 @@ __device__ __noinline__ void wave_push_hubs(const KArgs& a, ull* H, StepSlot* S,
 }
 
 // WriteMin filter (S3): hint[v] is a 32-bit upper bound of delta[v]
-// (HINT_NONE: none known), kept by the successful WriteMins with plain stores; a stale hint is
-// still an upper bound, since keys only fall. nd >= hint[v] means the WriteMin
-// cannot succeed, so the atomic is skipped. The hints take half the cache
+// (HINT_NONE: none known), kept by the successful WriteMins with plain
+// stores; a stale hint is still an upper bound, since keys only fall.
+// nd >= hint[v] means the WriteMin cannot succeed, so the atomic is skipped. The hints take half the cache
 // lines of the keys, and this read is the one random read of every arc.
 constexpr uint32_t HINT_NONE = 0xFFFFFFFFu;
 
@@ -991,8 +991,8 @@ __device__ __noinline__ ExtractOut phase_extract_dense_words(const KArgs& a, con
   if (threadIdx.x == 0) sh.fcnt = 0;
   __syncthreads();
   uint32_t* xc = a.xcount ? a.xcount + ld_agent(&tm.ctl->query) * (ull)a.n : nullptr;
-  // As in the lane walk: arguments in registers, global-address-space
-  // pointers, and unconditional reads.
+  // As in the dealt Extract above: arguments in registers,
+  // global-address-space pointers, and unconditional reads.
   const ull segcap = a.segcap;
   const bool snap = a.snapshot;
   const int32_t* perm = a.perm;
