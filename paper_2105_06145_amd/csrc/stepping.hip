@@ -14,8 +14,8 @@
 //                plus, while |Q| is small, an explicit list (Sec. 6, sparse
 //                mode), so small steps do not scan all n flags.
 //   S3 Relax     for u in F, v in N(u): WriteMin(delta[v], delta[u] + w) as a
-//                64-bit atomic min (Sec. 2 WriteMin), skipped when a 32-bit
-//                upper bound of delta[v] (hint[v]) already shows no
+//                64-bit atomic min (Sec. 2 WriteMin), skipped when a 16-bit
+//                coded upper bound of delta[v] (hint[v]) already shows no
 //                improvement. delta[u] is read when u's arcs are relaxed,
 //                so a u whose key another WriteMin of the same step has
 //                lowered already propagates the lower key.
@@ -174,7 +174,7 @@ struct KArgs {
   ull* dist_out;        // caller's rows, n_src x n, caller ids
   ull* dist_int;        // per-team internal rows (relabelled graphs), else NULL
   ull* bitmap;          // per team, nwords
-  uint32_t* hint;       // per team, n: upper bound of each key for the Relax filter (NULL: no filter)
+  uint16_t* hint;       // per team, n: upper bound of each key for the Relax filter (NULL: no filter)
   ull* key1;            // tournament-tree queue (NULL: flat array): per team, nwords (one node per bitmap word)
   ull* key2;            // per team, n2 (one node per 64 words)
   uint64_t n2;
@@ -247,7 +247,7 @@ struct Team {
   ull id, rank, T;  // team index, rank in the team, team size
   TeamCtl* ctl;
   ull* bitmap;
-  uint32_t* hint;
+  uint16_t* hint;
   ull* key1;  // tournament tree (NULL: flat array)
   ull* key2;
   ull* H;
@@ -615,14 +615,36 @@ __device__ __noinline__ void wave_push_hubs(const KArgs& a, ull* H, StepSlot* S,
   }
 }
 
-// WriteMin filter (S3): hint[v] is a 32-bit upper bound of delta[v]
-// (HINT_NONE: none known), kept by the successful WriteMins with plain
-// stores; a stale hint is still an upper bound, since keys only fall.
-// nd >= hint[v] means the WriteMin cannot succeed, so the atomic is skipped. The hints take half the cache
-// lines of the keys, and this read is the one random read of every arc.
-constexpr uint32_t HINT_NONE = 0xFFFFFFFFu;
+// WriteMin filter (S3): hint[v] is a 16-bit code of an upper bound of
+// delta[v] (HINT_NONE: none known), kept by the successful WriteMins with
+// plain stores; a stale hint is still an upper bound, since keys only fall.
+// nd >= value(hint[v]) means the WriteMin cannot succeed, so the atomic is
+// skipped. This read is the one random read of every arc, and the codes take
+// a quarter of the cache lines of the keys; rounding the bound up lets a few
+// more arcs through to the atomic.
+constexpr uint32_t HINT_NONE = 0xFFFFu;
 
-__device__ __forceinline__ uint32_t as_hint(ull d) { return d < (ull)HINT_NONE ? (uint32_t)d : HINT_NONE; }
+// The code: below 2048 the value itself; above, exponent e (1..31) in the
+// top 5 bits and m in the low 11, for the value (2048 + m) << (e - 1).
+// Values grow with the code.
+__device__ __forceinline__ ull hint_value(uint32_t c) {
+  const uint32_t e = c >> 11, m = c & 2047u;
+  return e == 0 ? (ull)m : ((ull)(2048u + m) << (e - 1));
+}
+// The smallest code whose value is at least d (HINT_NONE beyond the range).
+__device__ __forceinline__ uint16_t as_hint(ull d) {
+  if (d < 2048) return (uint16_t)d;
+  const int b = 63 - __clzll((long long)d);  // d's top bit, at least 11
+  uint32_t e = (uint32_t)(b - 10);
+  ull mf = d >> (e - 1);  // in [2048, 4095]
+  if ((mf << (e - 1)) < d) ++mf;
+  if (mf == 4096) {
+    ++e;
+    mf = 2048;
+  }
+  const uint32_t c = (e << 11) | (uint32_t)(mf - 2048);
+  return (e > 31 || c >= HINT_NONE) ? (uint16_t)HINT_NONE : (uint16_t)c;
+}
 
 // check = false skips the filter read (the hint is still kept): in
 // super-sparse steps with local expansion the work is a chain of hops, each
@@ -1215,7 +1237,7 @@ __device__ __forceinline__ void relax_batch(const KArgs& a, const Team& tm, ull*
     hv[k] = HINT_NONE;
   }
   if (filter) {
-    const gptr<uint32_t> hint = glob(tm.hint);
+    const gptr<uint16_t> hint = glob(tm.hint);
 #pragma unroll
     for (int k = 0; k < UNROLL; ++k)
       hv[k] = __hip_atomic_load(&hint[ev[k] == INF ? 0 : fv[k]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1230,7 +1252,7 @@ __device__ __forceinline__ void relax_batch(const KArgs& a, const Team& tm, ull*
     old[k] = 0;
     if (ev[k] == INF) continue;
     ++acc.edges;
-    if (hv[k] == HINT_NONE || nd[k] < (ull)hv[k]) pass |= 1u << k;
+    if (hv[k] == HINT_NONE || nd[k] < hint_value(hv[k])) pass |= 1u << k;
   }
   const gptr<ull> gdist = glob(dist);
 #pragma unroll
@@ -2121,7 +2143,7 @@ sssp_status ensure_workspace(sssp_graph* g, const sssp_tuning& tu, const Geometr
   const uint64_t n = (uint64_t)g->n, nt = geo.nteams;
   if (g->relabelled) SSSP_HIP_TRY(g->dist_int.alloc(nt * n * 8, st));
   SSSP_HIP_TRY(g->bitmap.alloc(nt * geo.nwords * 8, st));
-  SSSP_HIP_TRY(g->hint.alloc(nt * n * 4, st));
+  SSSP_HIP_TRY(g->hint.alloc(nt * n * 2, st));
   SSSP_HIP_TRY(g->tree.alloc(nt * (geo.nwords + (geo.nwords + 63) / 64) * 8, st));
   SSSP_HIP_TRY(g->hubmask.alloc(geo.nwords * 8, st));
   SSSP_HIP_TRY(g->bigmask.alloc(geo.nwords * 8, st));
@@ -2268,7 +2290,7 @@ sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uin
   a.sample_cap = tu.sample_cap;
   a.probe_cap = tu.probe_cap;
   a.filter = tu.no_filter ? 0u : 1u;
-  a.hint = tu.no_filter ? nullptr : (uint32_t*)g->hint.p;
+  a.hint = tu.no_filter ? nullptr : (uint16_t*)g->hint.p;
   a.snapshot = (p.flags & SSSP_SOLVE_SNAPSHOT_KEYS) ? 1u : 0u;
   // Local expansion reads current keys, so snapshot-key runs go without it.
   a.local_budget = (a.snapshot || tu.local_budget == 0xFFFFFFFFu) ? 0u : tu.local_budget;
