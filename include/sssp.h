@@ -272,6 +272,33 @@ sssp_status sssp_solve(const sssp_graph* g, const int32_t* sources, int32_t n_sr
                        uint64_t* dist, void* stream, sssp_stats* stats);
 
 /*
+ * sssp_solve for callers that cannot allocate device memory: code that must
+ * not call hipMalloc (stream capture, tight serving loops, harnesses that
+ * forbid allocation). Same arguments, results, semantics and errors as
+ * sssp_solve, and likewise returns after the stream has finished; it calls no
+ * hipMalloc, hipFree or other allocating routine. The solve's workspace
+ * (per-team distances, queue bitmaps and lists, key bounds, extraction
+ * segments, hub tasks, samples, counters and the kernel's argument block) is
+ * laid out in a static device array of SSSP_NOALLOC_SCRATCH_BYTES bytes inside
+ * the library, instead of the graph's own workspace (which this call neither
+ * uses nor changes). Each device the library runs on holds one such array
+ * until the process ends. The array keeps the last call's contents; the call
+ * clears what must start at zero. Calls on one device share the array, so
+ * the library serialises them with a per-device lock: a second call waits
+ * for the first to return.
+ * Limit: the workspace of one launch is about 8 n (relabelled graphs) +
+ * 10 n + n / 4 bytes per team, plus 12 bytes per extraction slot (at least
+ * 256 per workgroup, at least n in all), 16 (m / chunk_edges + m / hub_degree)
+ * bytes of hub tasks per team and 8 probe_cap bytes of samples per team
+ * (about 31 MB for one team at n = 2^20, m = 2^24). A launch that needs more
+ * is refused with INVALID_ARGUMENT before any device work.
+ * stats->device_ms is the call's host wall-clock time (no events are created).
+ */
+#define SSSP_NOALLOC_SCRATCH_BYTES (64ull << 20)
+sssp_status sssp_solve_noalloc(const sssp_graph* g, const int32_t* sources, int32_t n_src,
+                               const sssp_params* params, uint64_t* dist, void* stream, sssp_stats* stats);
+
+/*
  * Stream-ordered form of sssp_solve: the same computation (Alg. 1 per source,
  * all sources in one launch), for callers that overlap it with other work.
  * The call enqueues the launch on `stream` and returns without waiting. `sources` and `params` are

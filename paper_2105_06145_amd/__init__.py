@@ -24,7 +24,7 @@ from ._native import (SSSP_RULE_BF, SSSP_RULE_DELTA_STAR, SSSP_RULE_MIN, SSSP_RU
                       sssp_default_params, sssp_graph_create, sssp_graph_destroy, sssp_graph_info,
                       sssp_last_error, sssp_params, sssp_row_hash, sssp_server_destroy, sssp_server_poll,
                       sssp_server_start, sssp_server_stop, sssp_server_submit, sssp_solve, sssp_solve_async,
-                      sssp_solve_cancel, sssp_solve_query, sssp_solve_wait, sssp_stats,
+                      sssp_solve_noalloc, sssp_solve_cancel, sssp_solve_query, sssp_solve_wait, sssp_stats,
                       sssp_status_string, sssp_step_record, sssp_tuning)
 
 __all__ = ["Graph", "solve", "solve_async", "PendingSolve", "Server", "row_hash", "SSSPError", "to_numpy_u64", "RULES", "INF", "sssp_graph_create",
@@ -32,7 +32,7 @@ __all__ = ["Graph", "solve", "solve_async", "PendingSolve", "Server", "row_hash"
            "sssp_abi_version", "sssp_default_params", "sssp_params", "sssp_stats", "sssp_tuning",
            "sssp_step_record", "sssp_row_hash", "sssp_server_start", "sssp_server_submit", "sssp_server_poll",
            "sssp_server_stop", "sssp_server_destroy", "sssp_solve_async", "sssp_solve_query", "sssp_solve_wait",
-           "sssp_solve_cancel"]
+           "sssp_solve_cancel", "sssp_solve_noalloc"]
 
 INF = 0xFFFFFFFFFFFFFFFF
 RULES = {"rho": SSSP_RULE_RHO, "rho_exact": SSSP_RULE_RHO_EXACT, "delta": SSSP_RULE_DELTA_STAR,
@@ -190,13 +190,15 @@ def _params(rule, rho, delta, seed, tuning, snapshot_keys=False):
 
 def solve(g: Graph, sources, rule: str = "rho", rho: int = 1 << 20, delta: int = 1 << 13, seed: int = 1,
           max_steps: int = 0, tuning: dict | sssp_tuning | None = None, out=None, stream=None,
-          trace: int = 0, extract_counts: bool = False, snapshot_keys: bool = False):
+          trace: int = 0, extract_counts: bool = False, snapshot_keys: bool = False, noalloc: bool = False):
     """Solve from each source. Returns (dist, stats) where dist is a torch
     int64 CUDA tensor (n_src, n) holding uint64 bit patterns (-1 = unreachable)
     and stats is a dict; with trace > 0 stats["trace"] holds per-step records,
     with extract_counts=True stats["extract_counts"] a (n_src, n) int32 tensor.
     snapshot_keys=True relaxes with the keys vertices were extracted with, which
-    makes extraction sets independent of WriteMin ordering."""
+    makes extraction sets independent of WriteMin ordering. noalloc=True
+    calls sssp_solve_noalloc (workspace in the library's static scratch
+    array, no device allocation by the library)."""
     torch = _torch()
     src = np.ascontiguousarray(np.atleast_1d(np.asarray(sources)), dtype=np.int32)
     ns = int(src.shape[0])
@@ -216,10 +218,11 @@ def solve(g: Graph, sources, rule: str = "rho", rho: int = 1 << 20, delta: int =
         p.trace = tr.data_ptr()
         p.trace_capacity = int(trace)
     st = sssp_stats()
-    rc = sssp_solve(g._h, ctypes.c_void_p(src.ctypes.data), ns, p, ctypes.c_void_p(out.data_ptr()),
-                    _stream_ptr(stream), st)
+    entry = sssp_solve_noalloc if noalloc else sssp_solve
+    rc = entry(g._h, ctypes.c_void_p(src.ctypes.data), ns, p, ctypes.c_void_p(out.data_ptr()),
+               _stream_ptr(stream), st)
     if rc != N.SSSP_OK:
-        raise SSSPError(rc, "sssp_solve")
+        raise SSSPError(rc, entry.__name__)
     stats = st.as_dict()
     if counts is not None:
         stats["extract_counts"] = counts

@@ -20,6 +20,9 @@ HEADER = os.path.join(_REPO, "include", "sssp.h")
 HIPCC_FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
+# Bytes of the static workspace array behind sssp_solve_noalloc
+SSSP_NOALLOC_SCRATCH_BYTES = 64 << 20
+
 # Status codes (sssp_status)
 SSSP_OK = 0
 SSSP_ERR_INVALID_ARGUMENT = 1
@@ -123,6 +126,9 @@ def lib():
         L.sssp_solve.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(sssp_params), vp, vp,
                                  ctypes.POINTER(sssp_stats)]
         L.sssp_solve.restype = ctypes.c_int
+        L.sssp_solve_noalloc.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(sssp_params), vp, vp,
+                                         ctypes.POINTER(sssp_stats)]
+        L.sssp_solve_noalloc.restype = ctypes.c_int
         L.sssp_solve_async.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(sssp_params), vp, vp]
         L.sssp_solve_async.restype = ctypes.c_int
         L.sssp_solve_query.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
@@ -186,6 +192,13 @@ def sssp_graph_info(handle):
 def sssp_solve(handle, sources_ptr, n_src, params: sssp_params, dist_ptr, stream_ptr, stats: sssp_stats | None):
     return lib().sssp_solve(handle, sources_ptr, int(n_src), ctypes.byref(params) if params is not None else None,
                             dist_ptr, stream_ptr, ctypes.byref(stats) if stats is not None else None)
+
+
+def sssp_solve_noalloc(handle, sources_ptr, n_src, params: sssp_params, dist_ptr, stream_ptr,
+                       stats: sssp_stats | None):
+    return lib().sssp_solve_noalloc(handle, sources_ptr, int(n_src),
+                                    ctypes.byref(params) if params is not None else None, dist_ptr, stream_ptr,
+                                    ctypes.byref(stats) if stats is not None else None)
 
 
 def sssp_solve_async(handle, sources_ptr, n_src, params: sssp_params, dist_ptr, stream_ptr):

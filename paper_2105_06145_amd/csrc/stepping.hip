@@ -65,9 +65,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -2134,6 +2136,49 @@ Geometry make_geometry(const sssp_graph* g, const sssp_tuning& tu, uint32_t G, u
 
 uint64_t control_words(uint32_t nteams) { return (sizeof(GridCtl) + (uint64_t)nteams * sizeof(TeamCtl)) / 8; }
 
+// Device addresses of one launch's workspace: the graph's own buffers
+// (ensure_workspace) or slices of the static scratch array (carve_scratch).
+struct WsView {
+  void *dist_int, *bitmap, *hint, *tree, *hubmask, *bigmask, *F, *FD, *H, *L, *samples, *parts, *ctl, *args, *srcs;
+};
+
+WsView graph_view(const sssp_graph* g) {
+  return WsView{g->dist_int.p, g->bitmap.p, g->hint.p, g->tree.p, g->hubmask.p, g->bigmask.p, g->F.p, g->FD.p,
+                g->H.p,        g->L.p,      g->samples.p, g->parts.p, g->ctl.p,  g->args.p, g->srcs.p};
+}
+
+// Sizes in bytes of the workspace arrays of a launch, in WsView order.
+void workspace_sizes(const sssp_graph* g, const sssp_tuning& tu, const Geometry& geo, uint64_t n_src,
+                     uint64_t (&sz)[15]) {
+  const uint64_t n = (uint64_t)g->n, nt = geo.nteams;
+  sz[0] = g->relabelled ? nt * n * 8 : 0;                            // dist_int
+  sz[1] = nt * geo.nwords * 8;                                       // bitmap
+  sz[2] = nt * n * 2;                                                // hint
+  sz[3] = nt * (geo.nwords + (geo.nwords + 63) / 64) * 8;            // tree
+  sz[4] = geo.nwords * 8;                                            // hubmask
+  sz[5] = geo.nwords * 8;                                            // bigmask
+  sz[6] = (uint64_t)geo.G * geo.segcap * 4;                          // F
+  sz[7] = (uint64_t)geo.G * geo.segcap * 8;                          // FD
+  sz[8] = nt * geo.hcap * 16;                                        // H
+  sz[9] = nt * 2 * geo.lcap * 4;                                     // L
+  sz[10] = nt * (uint64_t)tu.probe_cap * 8;                          // samples
+  sz[11] = (uint64_t)geo.G * sizeof(Part);                           // parts
+  sz[12] = control_words(geo.nteams) * 8;                            // ctl
+  sz[13] = sizeof(KArgs);                                            // args
+  sz[14] = n_src * 4;                                                // srcs
+}
+
+// Hub flags (out-degree above hub_degree) and local-expansion flags (above
+// the local degree cap), one bit per vertex.
+hipError_t build_masks(const sssp_graph* g, const sssp_tuning& tu, const Geometry& geo, void* hubmask,
+                       void* bigmask, hipStream_t st) {
+  const uint64_t n = (uint64_t)g->n;
+  hubmask_kernel<<<1024, 256, 0, st>>>((const int64_t*)g->off.p, n, geo.nwords, tu.hub_degree, (ull*)hubmask);
+  hubmask_kernel<<<1024, 256, 0, st>>>((const int64_t*)g->off.p, n, geo.nwords, local_degree_cap(tu),
+                                       (ull*)bigmask);
+  return hipGetLastError();
+}
+
 sssp_status ensure_workspace(sssp_graph* g, const sssp_tuning& tu, const Geometry& geo, hipStream_t st) {
   if (g->ws_ready && g->ws_hub_degree == tu.hub_degree && g->ws_chunk == tu.chunk_edges &&
       g->ws_probe_cap >= tu.probe_cap && g->ws_G == geo.G && g->ws_teams == geo.nteams && g->ws_segcap == geo.segcap &&
@@ -2159,10 +2204,7 @@ sssp_status ensure_workspace(sssp_graph* g, const sssp_tuning& tu, const Geometr
     g->hargs = ::operator new(sizeof(KArgs), std::nothrow);
     if (!g->hargs) return fail(SSSP_ERR_OUT_OF_MEMORY, "kernel argument staging");
   }
-  hubmask_kernel<<<1024, 256, 0, st>>>((const int64_t*)g->off.p, n, geo.nwords, tu.hub_degree, (ull*)g->hubmask.p);
-  hubmask_kernel<<<1024, 256, 0, st>>>((const int64_t*)g->off.p, n, geo.nwords, local_degree_cap(tu),
-                                       (ull*)g->bigmask.p);
-  SSSP_HIP_TRY(hipGetLastError());
+  SSSP_HIP_TRY(build_masks(g, tu, geo, g->hubmask.p, g->bigmask.p, st));
   g->ws_ready = true;
   g->ws_hub_degree = tu.hub_degree;
   g->ws_chunk = tu.chunk_edges;
@@ -2219,7 +2261,8 @@ sssp_status check_params(const sssp_params* params, sssp_params& p, sssp_tuning&
   return SSSP_OK;
 }
 
-sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uint64_t* dist, hipStream_t st) {
+// Grid, teams and workspace geometry of a launch.
+sssp_status plan_launch(sssp_graph* g, Launch& L, uint32_t default_teams) {
   SSSP_HIP_TRY(hipSetDevice(g->device));
   int occ = 0;
   SSSP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, stepping_kernel, WG, 0));
@@ -2232,9 +2275,11 @@ sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uin
   L.geo = make_geometry(g, L.tu, L.G, L.nteams);
   if (L.tu.pull == 1 && !g->undirected)
     return fail(SSSP_ERR_INVALID_ARGUMENT, "pull = 1 needs a graph created with SSSP_UNDIRECTED");
-  sssp_status ws = ensure_workspace(g, L.tu, L.geo, st);
-  if (ws != SSSP_OK) return ws;
+  return SSSP_OK;
+}
 
+// Kernel arguments of a planned launch over workspace `w`.
+void fill_args(const sssp_graph* g, Launch& L, const WsView& w, uint64_t* dist) {
   const sssp_params& p = L.p;
   const sssp_tuning& tu = L.tu;
   const Geometry& geo = L.geo;
@@ -2245,21 +2290,22 @@ sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uin
   a.nwords = geo.nwords;
   a.off = (const int64_t*)g->off.p;
   a.edges = (const ull*)g->edges.p;
-  a.hubmask = (const ull*)g->hubmask.p;
-  a.bigmask = (const ull*)g->bigmask.p;
   a.perm = g->relabelled ? (const int32_t*)g->perm.p : nullptr;
   a.inv = g->relabelled ? (const int32_t*)g->inv.p : nullptr;
   a.dist_out = (ull*)dist;
-  a.dist_int = g->relabelled ? (ull*)g->dist_int.p : nullptr;
-  a.bitmap = (ull*)g->bitmap.p;
-  a.F = (int32_t*)g->F.p;
-  a.FD = (ull*)g->FD.p;
-  a.H = (ull*)g->H.p;
-  a.L = (int32_t*)g->L.p;
-  a.samples = (ull*)g->samples.p;
-  a.parts = (Part*)g->parts.p;
-  a.grid = (GridCtl*)g->ctl.p;
-  a.teams = (TeamCtl*)((char*)g->ctl.p + sizeof(GridCtl));
+  a.dist_int = g->relabelled ? (ull*)w.dist_int : nullptr;
+  a.bitmap = (ull*)w.bitmap;
+  a.hubmask = (const ull*)w.hubmask;
+  a.bigmask = (const ull*)w.bigmask;
+  a.F = (int32_t*)w.F;
+  a.FD = (ull*)w.FD;
+  a.H = (ull*)w.H;
+  a.L = (int32_t*)w.L;
+  a.samples = (ull*)w.samples;
+  a.parts = (Part*)w.parts;
+  a.grid = (GridCtl*)w.ctl;
+  a.teams = (TeamCtl*)((char*)w.ctl + sizeof(GridCtl));
+  a.srcs = (const int32_t*)w.srcs;
   a.xcount = p.extract_counts;
   a.trace = p.trace;
   a.trace_cap = p.trace ? p.trace_capacity : 0;
@@ -2275,7 +2321,7 @@ sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uin
     a.sparse_q = a.list_threshold;
     a.list_threshold = 0;
     a.n2 = (geo.nwords + 63) / 64;
-    a.key1 = (ull*)g->tree.p;
+    a.key1 = (ull*)w.tree;
     a.key2 = a.key1 + (uint64_t)L.nteams * geo.nwords;
   }
   a.tlimit = g->tick_khz * 1000ull * 20ull;  // 20 s per barrier wait
@@ -2290,7 +2336,7 @@ sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uin
   a.sample_cap = tu.sample_cap;
   a.probe_cap = tu.probe_cap;
   a.filter = tu.no_filter ? 0u : 1u;
-  a.hint = tu.no_filter ? nullptr : (uint16_t*)g->hint.p;
+  a.hint = tu.no_filter ? nullptr : (uint16_t*)w.hint;
   a.snapshot = (p.flags & SSSP_SOLVE_SNAPSHOT_KEYS) ? 1u : 0u;
   // Local expansion reads current keys, so snapshot-key runs go without it.
   a.local_budget = (a.snapshot || tu.local_budget == 0xFFFFFFFFu) ? 0u : tu.local_budget;
@@ -2301,34 +2347,54 @@ sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uin
   if ((uint64_t)g->m >= (uint64_t)tu.super_sparse_degree * (uint64_t)g->n) a.local_budget = 0;
   // Bidirectional relaxation reads current keys too; it needs symmetric arcs.
   a.pull = (!a.snapshot && g->undirected && tu.pull != 0xFFFFFFFFu && tu.pull != 0) ? 1u : 0u;
+}
+
+// Plan the launch, make sure the graph's workspace fits it, and fill the
+// kernel arguments.
+sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uint64_t* dist, hipStream_t st) {
+  sssp_status s = plan_launch(g, L, default_teams);
+  if (s != SSSP_OK) return s;
+  s = ensure_workspace(g, L.tu, L.geo, st);
+  if (s != SSSP_OK) return s;
+  fill_args(g, L, graph_view(g), dist);
   return SSSP_OK;
 }
 
-// Copy the kernel arguments to the device and clear the control blocks.
-hipError_t stage_launch(sssp_graph* g, const Launch& L, hipStream_t st) {
-  std::memcpy(g->hargs, &L.a, sizeof(KArgs));
-  hipError_t e = hipMemcpyAsync(g->args.p, g->hargs, sizeof(KArgs), hipMemcpyHostToDevice, st);
+// Copy the kernel arguments (staged in `hargs`, host memory that stays valid
+// until the copy has run) to `args_dev` and clear the control blocks.
+hipError_t stage_launch(const Launch& L, void* hargs, void* args_dev, void* ctl_dev, hipStream_t st) {
+  std::memcpy(hargs, &L.a, sizeof(KArgs));
+  hipError_t e = hipMemcpyAsync(args_dev, hargs, sizeof(KArgs), hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return e;
-  reset_control_kernel<<<64, 256, 0, st>>>((ull*)g->ctl.p, control_words(L.nteams));
+  reset_control_kernel<<<64, 256, 0, st>>>((ull*)ctl_dev, control_words(L.nteams));
   return hipGetLastError();
 }
 
-// Read the control blocks back (after the kernel finished) into stats.
+hipError_t stage_launch(sssp_graph* g, const Launch& L, hipStream_t st) {
+  return stage_launch(L, g->hargs, g->args.p, g->ctl.p, st);
+}
+
+// Read the control blocks at `ctl_dev` back (after the kernel finished) into
+// stats, a few team blocks at a time through a host buffer on the stack.
 // Returns the abort and step-limit indications.
-sssp_status collect_stats(sssp_graph* g, const Launch& L, hipStream_t st, sssp_stats* stats, bool& aborted,
-                          bool& step_limit, bool& cancelled) {
+sssp_status collect_stats(sssp_graph* g, const Launch& L, const void* ctl_dev, hipStream_t st, sssp_stats* stats,
+                          bool& aborted, bool& step_limit, bool& cancelled) {
+  constexpr uint32_t CHUNK = 8;
   GridCtl hg;
-  std::string hteams((size_t)L.nteams * sizeof(TeamCtl), '\0');
-  SSSP_HIP_TRY(hipMemcpyAsync(&hg, g->ctl.p, sizeof(GridCtl), hipMemcpyDeviceToHost, st));
-  SSSP_HIP_TRY(
-      hipMemcpyAsync(&hteams[0], (char*)g->ctl.p + sizeof(GridCtl), hteams.size(), hipMemcpyDeviceToHost, st));
+  TeamCtl hteams[CHUNK];
+  SSSP_HIP_TRY(hipMemcpyAsync(&hg, ctl_dev, sizeof(GridCtl), hipMemcpyDeviceToHost, st));
   SSSP_HIP_TRY(hipStreamSynchronize(st));
   aborted = hg.abort_flag != 0;
   step_limit = false;
   cancelled = false;
   for (uint32_t t = 0; t < L.nteams; ++t) {
-    TeamCtl tc;
-    std::memcpy(&tc, &hteams[(size_t)t * sizeof(TeamCtl)], sizeof(TeamCtl));
+    if (t % CHUNK == 0) {
+      const uint32_t k = std::min(CHUNK, L.nteams - t);
+      SSSP_HIP_TRY(hipMemcpyAsync(hteams, (const char*)ctl_dev + sizeof(GridCtl) + (size_t)t * sizeof(TeamCtl),
+                                  (size_t)k * sizeof(TeamCtl), hipMemcpyDeviceToHost, st));
+      SSSP_HIP_TRY(hipStreamSynchronize(st));
+    }
+    const TeamCtl& tc = hteams[t % CHUNK];
     step_limit |= (tc.status & ST_STEP_LIMIT) != 0;
     cancelled |= (tc.status & ST_CANCELLED) != 0;
     if (!stats) continue;
@@ -2350,6 +2416,11 @@ sssp_status collect_stats(sssp_graph* g, const Launch& L, hipStream_t st, sssp_s
   }
   if (stats) stats->teams = L.nteams;
   return SSSP_OK;
+}
+
+sssp_status collect_stats(sssp_graph* g, const Launch& L, hipStream_t st, sssp_stats* stats, bool& aborted,
+                          bool& step_limit, bool& cancelled) {
+  return collect_stats(g, L, g->ctl.p, st, stats, aborted, step_limit, cancelled);
 }
 
 // Checksum of one distance row (the same mix as the serving kernel's).
@@ -2426,6 +2497,51 @@ sssp_status check_solve_args(const sssp_graph* gc, const int32_t* sources, int32
   return SSSP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Workspace without allocation (sssp_solve_noalloc): a static device array.
+// In host code `scratch` names a host-side stand-in, not device memory; its
+// device address is looked up once per device (scratch_address) and only
+// that address is ever handed to kernels or copies.
+
+static __device__ __align__(256) unsigned char scratch[SSSP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu[NOALLOC_MAX_DEVICES];     // one call at a time per device
+void* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};    // device address of `scratch` per device
+
+// Device address of this device's copy of `scratch` (the device must be
+// current; the caller holds g_scratch_mu[dev]).
+sssp_status scratch_address(int dev, char** out) {
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SSSP_ERR_DEVICE, std::string("scratch array address: ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = p;
+  }
+  *out = (char*)g_scratch_dev[dev];
+  return SSSP_OK;
+}
+
+// Lay the launch's workspace out in the scratch array at `base` (256-byte
+// aligned slices, in WsView order).
+sssp_status carve_scratch(const sssp_graph* g, const Launch& L, uint64_t n_src, char* base, WsView& w) {
+  uint64_t sz[15];
+  workspace_sizes(g, L.tu, L.geo, n_src, sz);
+  void** slot[15] = {&w.dist_int, &w.bitmap, &w.hint, &w.tree, &w.hubmask, &w.bigmask, &w.F,  &w.FD,
+                     &w.H,        &w.L,      &w.samples, &w.parts, &w.ctl, &w.args, &w.srcs};
+  uint64_t off = 0;
+  for (int i = 0; i < 15; ++i) {
+    *slot[i] = base + off;
+    off += (std::max<uint64_t>(sz[i], 8) + 255) / 256 * 256;
+  }
+  if (off > SSSP_NOALLOC_SCRATCH_BYTES)
+    return fail(SSSP_ERR_INVALID_ARGUMENT, "the solve needs " + std::to_string(off) +
+                                               " bytes of workspace; the scratch array holds " +
+                                               std::to_string((uint64_t)SSSP_NOALLOC_SCRATCH_BYTES));
+  return SSSP_OK;
+}
+
 // An asynchronous solve between sssp_solve_async and sssp_solve_wait.
 struct PendingSolve {
   Launch L;
@@ -2497,6 +2613,66 @@ sssp_status sssp_solve(const sssp_graph* gc, const int32_t* sources, int32_t n_s
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
   return s;
+}
+
+sssp_status sssp_solve_noalloc(const sssp_graph* gc, const int32_t* sources, int32_t n_src,
+                               const sssp_params* params, uint64_t* dist, void* stream, sssp_stats* stats) {
+  last_error().clear();
+  sssp_status as = check_solve_args(gc, sources, n_src, dist);
+  if (as != SSSP_OK) return as;
+  Launch L;
+  sssp_status ps = check_params(params, L.p, L.tu);
+  if (ps != SSSP_OK) return ps;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (n_src == 0) return SSSP_OK;
+  sssp_graph* g = const_cast<sssp_graph*>(gc);
+  if (g->device < 0 || g->device >= NOALLOC_MAX_DEVICES)
+    return fail(SSSP_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu[g->device]);
+  SSSP_HIP_TRY(hipSetDevice(g->device));
+  char* base = nullptr;
+  sssp_status s = scratch_address(g->device, &base);
+  if (s != SSSP_OK) return s;
+  {
+    int occ = 0;
+    SSSP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, stepping_kernel, WG, 0));
+    const uint32_t G = std::max(1u, std::min<uint32_t>(L.tu.blocks_per_cu, (uint32_t)std::max(occ, 1))) *
+                       (uint32_t)g->cus;
+    s = plan_launch(g, L, auto_teams(n_src, G));
+    if (s != SSSP_OK) return s;
+  }
+  WsView w;
+  s = carve_scratch(g, L, (uint64_t)n_src, base, w);
+  if (s != SSSP_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  fill_args(g, L, w, dist);
+  L.a.n_src = n_src;
+  L.a.cancel = nullptr;
+  // Host staging of the arguments: this frame outlives the copy, since the
+  // call waits for the stream before returning.
+  KArgs staged;
+  const auto t0 = std::chrono::steady_clock::now();
+  hipError_t e = build_masks(g, L.tu, L.geo, w.hubmask, w.bigmask, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(w.srcs, sources, (size_t)n_src * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = stage_launch(L, &staged, w.args, w.ctl, st);
+  if (e == hipSuccess) {
+    const KArgs* dargs = (const KArgs*)w.args;
+    void* kargs[] = {(void*)&dargs};
+    e = hipLaunchCooperativeKernel((const void*)stepping_kernel, dim3(L.G), dim3(WG), kargs, 0, st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(st);
+    return fail(from_hip(e), std::string("solve_noalloc: ") + hipGetErrorString(e));
+  }
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  bool aborted = false, step_limit = false, cancelled = false;
+  s = collect_stats(g, L, w.ctl, st, stats, aborted, step_limit, cancelled);
+  if (s != SSSP_OK) return s;
+  if (stats) stats->device_ms = ms;
+  if (aborted) return fail(SSSP_ERR_DEVICE, "grid barrier timed out (workgroups not co-resident?)");
+  if (step_limit) return fail(SSSP_ERR_STEP_LIMIT, "max_steps reached with a non-empty queue");
+  return SSSP_OK;
 }
 
 sssp_status sssp_solve_async(const sssp_graph* gc, const int32_t* sources, int32_t n_src,

@@ -169,3 +169,13 @@ def test_graph_create_rejects_unknown_flag_bits():
     ptrs = [ctypes.c_void_p(a.ctypes.data) for a in (off, tgt, w)]
     rc = lib.sssp_graph_create(2, 2, N.SSSP_OFFSETS_I64, *ptrs, N.SSSP_INPUT_HOST | 0x100, None, ctypes.byref(h))
     assert rc == N.SSSP_ERR_INVALID_ARGUMENT and "flag" in N.sssp_last_error()
+
+
+def test_noalloc_solve_null_arguments_and_limit():
+    # Every check here returns before any device call.
+    p = N.sssp_default_params()
+    assert N.sssp_solve_noalloc(None, None, 1, p, None, None, None) == N.SSSP_ERR_INVALID_ARGUMENT
+    assert "NULL" in N.sssp_last_error()
+    text = open(HEADER).read()
+    m = re.search(r"#define SSSP_NOALLOC_SCRATCH_BYTES \((\d+)ull << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == N.SSSP_NOALLOC_SCRATCH_BYTES
