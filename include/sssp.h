@@ -134,7 +134,11 @@ typedef struct {
                              SSSP_UNDIRECTED. 0 = library default (off), 1 = on
                              (INVALID_ARGUMENT on other graphs), 0xFFFFFFFF = off; always off
                              with SSSP_SOLVE_SNAPSHOT_KEYS */
-  uint32_t reserved;
+  uint32_t group_max;     /* serving only: the most teams that solve one request together.
+                             A request is dispatched to k idle teams, k the largest power of
+                             two with k * (waiting requests) <= idle teams, at most group_max,
+                             so few requests in flight get most of the grid each (0 = all of
+                             the server's teams; 1 = one team per request) */
   uint32_t queue;         /* LaB-PQ structure (Sec. 4): 0 = the flat array (a bitmap, plus an
                              explicit list while the queue is small; Sec. 4.3, 6); 1 = a
                              tournament tree (Sec. 4.2, Alg. 2) of fan-out 64 over the bitmap:
@@ -343,11 +347,26 @@ sssp_status sssp_row_hash(const uint64_t* dist, int64_t n, void* stream, uint64_
 /*
  * Serving: a persistent launch that takes single-source requests from a ring
  * in host memory while it runs (continuous batching). Its workgroups form
- * tuning.teams teams (default: teams of 16 workgroups); a free team takes the
- * next posted request, solves it (Alg. 1) into the caller's row, and marks it
- * done, so requests join and leave the running batch one by one.
+ * tuning.teams teams (default: teams of 16 workgroups, at most 64 teams).
+ * Each posted request is dispatched to a group of idle teams, which solves
+ * it (Alg. 1) into its row and marks it done, so requests join and leave the
+ * running batch one by one. The group is elastic: k idle teams, k the largest
+ * power of two such that every waiting request still finds a team (at most
+ * tuning.group_max), so a request that arrives at a quiet server gets most of
+ * the grid, and under load each team solves its own request.
  *
- * sssp_server_start launches the kernel and returns at once. The launch runs
+ * Two ways to admit requests:
+ *   - sssp_server_start: the caller owns `rows` result rows and names the row
+ *     of each request (sssp_server_submit); a request is admitted when the
+ *     caller has a free row to give it.
+ *   - sssp_server_start_budget: admission by a device-memory budget. The
+ *     launch's workspace and as many result rows as fit come out of the
+ *     budget; sssp_server_enqueue always accepts a request, which waits in a
+ *     host queue until a row is free; a finished request holds its row until
+ *     the caller reads it (sssp_server_result) and gives it back
+ *     (sssp_server_release), which admits the next waiting request.
+ *
+ * Both start calls launch the kernel and return at once. The launch runs
  * on a stream the library creates with a hardware queue of its own (HIP
  * otherwise shares a few queues among all streams, and a queue runs its
  * kernels in order, so a persistent launch would hold back unrelated work);
@@ -363,8 +382,10 @@ sssp_status sssp_row_hash(const uint64_t* dist, int64_t n, void* stream, uint64_
  *   ring_capacity  most requests posted but not yet taken by a team.
  *   flags    SSSP_SERVE_HASH: also compute each finished row's checksum
  *            (as sssp_row_hash), returned by sssp_server_poll.
- *   idle_ms  a team waiting longer than this for a request ends the launch
- *            (0 = 60000).
+ *   idle_ms  a team that has waited longer than this for a request closes
+ *            the launch: no further request is dispatched, the teams leave
+ *            once their current requests are done, and submit / enqueue
+ *            return DEVICE from then on (0 = 60000).
  * tuning.blocks_per_cu sets the grid (default 2 per compute unit, half of the
  * kernel's occupancy of 4, so that other kernels such as copies still find
  * room while the server runs). Servers on several graphs may run side by side
@@ -373,7 +394,8 @@ sssp_status sssp_row_hash(const uint64_t* dist, int64_t n, void* stream, uint64_
  * launched meanwhile wait for free slots: with servers holding all of them, a
  * copy on another stream waits until a server ends. While a server runs,
  * sssp_solve and another server on the same graph are refused.
- * One host thread drives a server (submit, poll and stop do not lock).
+ * One host thread drives a server (submit, enqueue, poll, release and stop do
+ * not lock).
  */
 #define SSSP_SERVE_HASH 0x1u
 typedef struct sssp_server sssp_server; /* opaque */
@@ -382,30 +404,81 @@ sssp_status sssp_server_start(const sssp_graph* g, const sssp_params* params, ui
                               uint32_t ring_capacity, uint32_t flags, uint32_t idle_ms, void* stream,
                               sssp_server** out);
 
+/* Start a server that admits requests by a device-memory budget of
+ * budget_bytes: the launch's workspace (per team: keys, queue bitmap and
+ * lists, key bounds, hub tasks, samples; per workgroup: extraction segments)
+ * is counted first, and the rest holds floor(rest / (8 n)) result rows (at
+ * most 65536), allocated here and owned by the server; the ring holds as many
+ * entries as rows. OUT_OF_MEMORY when the budget holds no row (the detail
+ * gives the workspace and row sizes). Other arguments as sssp_server_start. */
+sssp_status sssp_server_start_budget(const sssp_graph* g, const sssp_params* params, uint64_t budget_bytes,
+                                     uint32_t flags, uint32_t idle_ms, void* stream, sssp_server** out);
+
 /* Post one request (host call; validated here). *ticket numbers requests in
  * posting order from 0; the request waits in ring entry ticket % capacity
  * until a team takes it. INVALID_ARGUMENT when that entry still holds an
  * untaken request (ring full), the row holds a request not yet polled done,
- * the server is stopped, or source / row is out of range; DEVICE when the
- * launch has already ended (its idle limit passed).
- * A request posted while the last teams are leaving at the idle limit is
- * never served: callers that let a server idle should poll with a deadline. */
+ * the server is stopped or started with a budget, or source / row is out of
+ * range; DEVICE when the launch takes no more requests (its idle limit
+ * passed, or it ended). */
 sssp_status sssp_server_submit(sssp_server* s, int32_t source, uint32_t row, uint64_t* ticket);
+
+/* Budget servers: queue one request (host call; validated here). It is
+ * admitted at once when a result row is free, else when one is released;
+ * *ticket numbers requests in enqueue order from 0 (the order they are
+ * admitted in). INVALID_ARGUMENT for a bad source, a stopped server or one
+ * started with caller rows; DEVICE when the launch takes no more requests. */
+sssp_status sssp_server_enqueue(sssp_server* s, int32_t source, uint64_t* ticket);
 
 /* Collect up to `max` requests finished since the last poll: their tickets
  * and, with SSSP_SERVE_HASH, their row checksums (hashes may be NULL).
  * *count receives the number returned. Completion order may differ from
- * posting order. */
+ * posting order. DEVICE (with *count = 0) when the launch has ended while
+ * requests were still unfinished or waiting (after its idle limit or an
+ * error), so that no caller waits for them forever. */
 sssp_status sssp_server_poll(sssp_server* s, uint64_t* tickets, uint64_t* hashes, uint32_t max, uint32_t* count);
+
+/* Budget servers: *row = the device address of the n distances of a request
+ * that sssp_server_poll has returned and that is not yet released (valid
+ * until sssp_server_release). INVALID_ARGUMENT for any other ticket. */
+sssp_status sssp_server_result(sssp_server* s, uint64_t ticket, const uint64_t** row);
+
+/* Budget servers: give the row of a finished request back to the budget (the
+ * caller has finished reading it, including copies it enqueued); waiting
+ * requests are admitted into the free rows. INVALID_ARGUMENT for a ticket
+ * that is not finished and held. */
+sssp_status sssp_server_release(sssp_server* s, uint64_t ticket);
+
+/* Budget servers: copy the row of a finished, held request into dst (n
+ * uint64 entries; device or host memory) on `stream`, wait for the copy, and
+ * release the row (as sssp_server_release). `stream` must not be the legacy
+ * NULL stream while the server runs (it would wait for the launch to end). */
+sssp_status sssp_server_take(sssp_server* s, uint64_t ticket, uint64_t* dst, void* stream);
+
+typedef struct {
+  uint64_t rows;         /* result rows (caller's or drawn from the budget) */
+  uint64_t row_bytes;    /* bytes per row (8 n) */
+  uint64_t budget_bytes; /* budget servers: the budget; else 0 */
+  uint64_t teams;        /* teams of the launch */
+  uint64_t waiting;      /* budget servers: requests queued, not yet admitted */
+  uint64_t admitted;     /* requests posted to the launch and not yet polled finished */
+  uint64_t held;         /* budget servers: finished requests whose rows are not yet released */
+  uint64_t free_rows;    /* rows free for the next admission */
+  uint64_t workspace_bytes; /* device bytes of the launch's workspace (counted in the budget) */
+} sssp_server_load;
+
+/* Current admission state of a server (host bookkeeping; no device call). */
+sssp_status sssp_server_counts(const sssp_server* s, sssp_server_load* load);
 
 /* Close the ring: the kernel finishes every posted request, then ends; waits
  * for it and fills stats (totals over all requests; device_ms = the launch's
- * lifetime). Requests finished meanwhile can still be polled. Idempotent. */
+ * lifetime). Requests finished meanwhile can still be polled; requests still
+ * waiting for admission on a budget server are dropped. Idempotent. */
 sssp_status sssp_server_stop(sssp_server* s, sssp_stats* stats);
 
-/* Stop (if needed) and release the server. NULL is accepted. Freeing its
- * pinned ring waits for all work on the device, so stop every server that
- * shares the device before destroying any of them. */
+/* Stop (if needed) and release the server, with its rows on a budget server.
+ * NULL is accepted. Freeing its pinned ring waits for all work on the device,
+ * so stop every server that shares the device before destroying any of them. */
 sssp_status sssp_server_destroy(sssp_server* s);
 
 /* Static description of a status code. */

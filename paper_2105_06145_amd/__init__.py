@@ -24,7 +24,8 @@ from ._native import (SSSP_RULE_BF, SSSP_RULE_DELTA_STAR, SSSP_RULE_MIN, SSSP_RU
                       sssp_default_params, sssp_graph_create, sssp_graph_destroy, sssp_graph_info,
                       sssp_last_error, sssp_params, sssp_row_hash, sssp_server_destroy, sssp_server_poll,
                       sssp_server_start, sssp_server_stop, sssp_server_submit, sssp_solve, sssp_solve_async,
-                      sssp_solve_noalloc, sssp_solve_cancel, sssp_solve_query, sssp_solve_wait, sssp_stats,
+                      sssp_solve_noalloc, sssp_solve_cancel, sssp_server_start_budget, sssp_server_enqueue,
+                      sssp_server_result, sssp_server_release, sssp_server_take, sssp_server_counts, sssp_solve_query, sssp_solve_wait, sssp_stats,
                       sssp_status_string, sssp_step_record, sssp_tuning)
 
 __all__ = ["Graph", "solve", "solve_async", "PendingSolve", "Server", "row_hash", "SSSPError", "to_numpy_u64", "RULES", "INF", "sssp_graph_create",
@@ -32,7 +33,9 @@ __all__ = ["Graph", "solve", "solve_async", "PendingSolve", "Server", "row_hash"
            "sssp_abi_version", "sssp_default_params", "sssp_params", "sssp_stats", "sssp_tuning",
            "sssp_step_record", "sssp_row_hash", "sssp_server_start", "sssp_server_submit", "sssp_server_poll",
            "sssp_server_stop", "sssp_server_destroy", "sssp_solve_async", "sssp_solve_query", "sssp_solve_wait",
-           "sssp_solve_cancel", "sssp_solve_noalloc"]
+           "sssp_solve_cancel", "sssp_solve_noalloc", "BudgetServer", "sssp_server_start_budget",
+           "sssp_server_enqueue", "sssp_server_result", "sssp_server_release", "sssp_server_take",
+           "sssp_server_counts"]
 
 INF = 0xFFFFFFFFFFFFFFFF
 RULES = {"rho": SSSP_RULE_RHO, "rho_exact": SSSP_RULE_RHO_EXACT, "delta": SSSP_RULE_DELTA_STAR,
@@ -340,6 +343,87 @@ class Server:
         if rc != N.SSSP_OK:
             raise SSSPError(rc, "sssp_server_poll")
         return [(self._t[i], self._h[i]) for i in range(c)]
+
+    def stop(self) -> dict:
+        st = sssp_stats()
+        rc = sssp_server_stop(self._s, st)
+        if rc != N.SSSP_OK:
+            raise SSSPError(rc, "sssp_server_stop")
+        self.stats = st.as_dict()
+        return self.stats
+
+    def close(self):
+        if getattr(self, "_s", None) is not None:
+            sssp_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BudgetServer:
+    """A serving launch that admits requests by a device-memory budget
+    (sssp_server_start_budget): the launch's workspace and as many result
+    rows as fit come out of `budget_bytes`; enqueue() always accepts a
+    request, which waits until a row is free; a finished request (poll())
+    holds its row until take() copies it out or release() gives it back.
+    Keep GPU work off the default (NULL) stream while it runs (see Server)."""
+
+    def __init__(self, g: Graph, budget_bytes: int, rule: str = "rho", rho: int = 1 << 20, delta: int = 1 << 13,
+                 seed: int = 1, tuning: dict | sssp_tuning | None = None, hash_rows: bool = False, idle_ms: int = 0,
+                 stream=None):
+        self.g = g
+        self.stream = stream if stream is not None else _torch().cuda.current_stream()
+        p, self._tun = _params(rule, rho, delta, seed, tuning)
+        rc, self._s = sssp_server_start_budget(g._h, p, int(budget_bytes), N.SSSP_SERVE_HASH if hash_rows else 0,
+                                               idle_ms, ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != N.SSSP_OK:
+            raise SSSPError(rc, "sssp_server_start_budget")
+        self.rows = self.counts()["rows"]
+        self._t = (ctypes.c_uint64 * self.rows)()
+        self._h = (ctypes.c_uint64 * self.rows)()
+        self.stats = None
+
+    def enqueue(self, source: int) -> int:
+        rc, t = sssp_server_enqueue(self._s, source)
+        if rc != N.SSSP_OK:
+            raise SSSPError(rc, "sssp_server_enqueue")
+        return t
+
+    def poll(self) -> list[tuple[int, int]]:
+        """(ticket, row checksum) of the requests finished since the last poll."""
+        rc, c = sssp_server_poll(self._s, self._t, self._h, self.rows)
+        if rc != N.SSSP_OK:
+            raise SSSPError(rc, "sssp_server_poll")
+        return [(self._t[i], self._h[i]) for i in range(c)]
+
+    def take(self, ticket: int, out=None, stream=None):
+        """Copy a finished request's distances into `out` (an int64 CUDA
+        tensor of n elements, allocated if None) and release its row."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.g.n, dtype=torch.int64, device="cuda")
+        elif out.dtype != torch.int64 or out.numel() != self.g.n or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int64 CUDA tensor with n elements")
+        s = stream if stream is not None else torch.cuda.current_stream()
+        rc = sssp_server_take(self._s, ticket, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(s.cuda_stream))
+        if rc != N.SSSP_OK:
+            raise SSSPError(rc, "sssp_server_take")
+        return out
+
+    def release(self, ticket: int):
+        rc = sssp_server_release(self._s, ticket)
+        if rc != N.SSSP_OK:
+            raise SSSPError(rc, "sssp_server_release")
+
+    def counts(self) -> dict:
+        rc, ld = sssp_server_counts(self._s)
+        if rc != N.SSSP_OK:
+            raise SSSPError(rc, "sssp_server_counts")
+        return ld.as_dict()
 
     def stop(self) -> dict:
         st = sssp_stats()

@@ -59,7 +59,7 @@ class sssp_tuning(ctypes.Structure):
                 ("sample_cap", ctypes.c_uint32), ("probe_cap", ctypes.c_uint32),
                 ("no_filter", ctypes.c_uint32), ("teams", ctypes.c_uint32),
                 ("local_budget", ctypes.c_uint32), ("super_sparse_degree", ctypes.c_uint32),
-                ("pull", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("queue", ctypes.c_uint32),
+                ("pull", ctypes.c_uint32), ("group_max", ctypes.c_uint32), ("queue", ctypes.c_uint32),
                 ("reserved2", ctypes.c_uint32)]
 
 
@@ -90,6 +90,15 @@ class sssp_stats(ctypes.Structure):
         d["phase_ms"] = list(self.phase_ms)
         d["relax_wg_ms"] = list(self.relax_wg_ms)
         return d
+
+
+class sssp_server_load(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_uint64), ("row_bytes", ctypes.c_uint64), ("budget_bytes", ctypes.c_uint64),
+                ("teams", ctypes.c_uint64), ("waiting", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
+                ("held", ctypes.c_uint64), ("free_rows", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 def build(force: bool = True) -> str:
@@ -149,6 +158,19 @@ def lib():
         L.sssp_server_start.argtypes = [vp, ctypes.POINTER(sssp_params), vp, ctypes.c_uint32, ctypes.c_uint32,
                                         ctypes.c_uint32, ctypes.c_uint32, vp, ctypes.POINTER(vp)]
         L.sssp_server_start.restype = ctypes.c_int
+        L.sssp_server_start_budget.argtypes = [vp, ctypes.POINTER(sssp_params), ctypes.c_uint64, ctypes.c_uint32,
+                                               ctypes.c_uint32, vp, ctypes.POINTER(vp)]
+        L.sssp_server_start_budget.restype = ctypes.c_int
+        L.sssp_server_enqueue.argtypes = [vp, ctypes.c_int32, u64p]
+        L.sssp_server_enqueue.restype = ctypes.c_int
+        L.sssp_server_result.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(vp)]
+        L.sssp_server_result.restype = ctypes.c_int
+        L.sssp_server_release.argtypes = [vp, ctypes.c_uint64]
+        L.sssp_server_release.restype = ctypes.c_int
+        L.sssp_server_take.argtypes = [vp, ctypes.c_uint64, vp, vp]
+        L.sssp_server_take.restype = ctypes.c_int
+        L.sssp_server_counts.argtypes = [vp, ctypes.POINTER(sssp_server_load)]
+        L.sssp_server_counts.restype = ctypes.c_int
         L.sssp_server_submit.argtypes = [vp, ctypes.c_int32, ctypes.c_uint32, u64p]
         L.sssp_server_submit.restype = ctypes.c_int
         L.sssp_server_poll.argtypes = [vp, u64p, u64p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
@@ -234,6 +256,43 @@ def sssp_server_start(handle, params: sssp_params, dist_ptr, rows, ring_capacity
     rc = lib().sssp_server_start(handle, ctypes.byref(params) if params is not None else None, dist_ptr, int(rows),
                                  int(ring_capacity), int(flags), int(idle_ms), stream_ptr, ctypes.byref(s))
     return rc, (s if rc == SSSP_OK else None)
+
+
+def sssp_server_start_budget(handle, params: sssp_params, budget_bytes, flags, idle_ms, stream_ptr):
+    """Returns (status, server handle or None)."""
+    s = ctypes.c_void_p()
+    rc = lib().sssp_server_start_budget(handle, ctypes.byref(params) if params is not None else None,
+                                        int(budget_bytes), int(flags), int(idle_ms), stream_ptr, ctypes.byref(s))
+    return rc, (s if rc == SSSP_OK else None)
+
+
+def sssp_server_enqueue(server, source):
+    """Returns (status, ticket)."""
+    t = ctypes.c_uint64()
+    rc = lib().sssp_server_enqueue(server, int(source), ctypes.byref(t))
+    return rc, t.value
+
+
+def sssp_server_result(server, ticket):
+    """Returns (status, device address of the row or None)."""
+    p = ctypes.c_void_p()
+    rc = lib().sssp_server_result(server, int(ticket), ctypes.byref(p))
+    return rc, (p.value if rc == SSSP_OK else None)
+
+
+def sssp_server_release(server, ticket):
+    return lib().sssp_server_release(server, int(ticket))
+
+
+def sssp_server_take(server, ticket, dst_ptr, stream_ptr):
+    return lib().sssp_server_take(server, int(ticket), dst_ptr, stream_ptr)
+
+
+def sssp_server_counts(server):
+    """Returns (status, sssp_server_load)."""
+    ld = sssp_server_load()
+    rc = lib().sssp_server_counts(server, ctypes.byref(ld))
+    return rc, ld
 
 
 def sssp_server_submit(server, source, row):

@@ -69,9 +69,11 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "internal.h"
@@ -128,6 +130,16 @@ struct TeamCtl {
   ull sel_min, sel_max, sel_prefix, sel_k, sel_top;
   ull sel_hist[256];
   ull pending;   // ticket + 1 of a finished request not yet published (0: none)
+  // Serving groups. A request is solved by a group of k teams: the group
+  // uses its leader's workspace and this block of the leader's, meets on the
+  // leader's group barrier (garrive / ggen; counts only grow, so a group
+  // starts from the count it finds) and lists its member teams in gteam.
+  // The mailbox (mb_*) is this team's assignment, written by whichever team
+  // dispatched it; mb_seq grows by one per assignment.
+  ull mb_seq, mb_leader, mb_k, mb_idx, mb_base, mb_exit;
+  uint32_t gteam[64];
+  Line garrive;
+  Line ggen;
   alignas(128) StepSlot slot[3];
 };
 
@@ -145,6 +157,11 @@ struct GridCtl {
   alignas(128) unsigned abort_flag;
   unsigned cancelled;  // some team saw the host's cancel flag: teams claim no more sources
   ull ngroups;
+  // Serving: the dispatcher's lock, the idle teams (bit t = team t) and the
+  // closing word (set when a team's idle limit passes: no more assignments).
+  alignas(128) unsigned lock;
+  ull free_mask;
+  ull closing;
 };
 
 constexpr unsigned ST_STEP_LIMIT = 1;
@@ -221,10 +238,10 @@ struct KArgs {
   uint64_t ring_cap;
   uint64_t nrows;              // rows of dist_out
   uint64_t idle_ticks;         // longest wait for a request
+  uint32_t* dev_closed;        // host: set to 1 once the launch takes no more requests (idle limit)
+  uint32_t group_max;          // serving: most teams that solve one request together (a power of two)
   const uint32_t* cancel;      // host: nonzero asks the solve to stop (asynchronous solves), or NULL
 };
-
-constexpr ull SERVE_EXIT = ~0ull;
 
 struct Shared {
   ull beg[WG];
@@ -257,8 +274,12 @@ struct Team {
   ull* samples;
   int32_t* Fb;  // this workgroup's F segment: vertices
   ull* FDb;     // and their keys at extraction
+  ull k, Tteam;  // teams working on the current source and workgroups per team (T = k * Tteam)
+  ull own;       // this workgroup's own team (serving groups: tm.id is the group's leader)
   // barrier
-  ull epoch;
+  ull epoch;      // first-level barriers passed
+  ull l2_epoch;   // second-level barriers passed since l2_base was taken
+  ull l2_base;    // second-level arrival count when the current group formed
   ull* l1_arrive;
   ull* l1_gen;
   ull l1_size;
@@ -474,6 +495,10 @@ __device__ bool team_sync(const KArgs& a, Shared& sh, Team& tm, Serial serial) {
   __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached L2
   __syncthreads();
   ++tm.epoch;
+  if (tm.l2_arrive) ++tm.l2_epoch;
+  // Second-level target: arrivals counted from the group's base; the release
+  // publishes the target itself, so the value only grows across groups.
+  const ull target2 = tm.l2_base + tm.l2_epoch * tm.l2_size;
   if (threadIdx.x == 0) {
     sh.last = 0;
     if (tm.member_release) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -483,11 +508,11 @@ __device__ bool team_sync(const KArgs& a, Shared& sh, Team& tm, Serial serial) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       if (tm.l2_arrive) {
         const ull p2 = atom_add(tm.l2_arrive, 1ull);
-        if (p2 == tm.epoch * tm.l2_size - 1ull) {
+        if (p2 == target2 - 1ull) {
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
           sh.last = 1;
         } else {
-          spin_until(a, tm.l2_gen, tm.epoch);
+          spin_until(a, tm.l2_gen, target2);
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
           st_agent(tm.l1_gen, tm.epoch);
         }
@@ -507,7 +532,7 @@ __device__ bool team_sync(const KArgs& a, Shared& sh, Team& tm, Serial serial) {
     __syncthreads();
     if (threadIdx.x == 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      if (tm.l2_arrive) st_agent(tm.l2_gen, tm.epoch);
+      if (tm.l2_arrive) st_agent(tm.l2_gen, target2);
       st_agent(tm.l1_gen, tm.epoch);
     }
   }
@@ -1634,7 +1659,9 @@ __device__ __noinline__ void step_bookkeeping(const KArgs& a, StepSlot* S, ull t
   TeamCtl* tc = tm.ctl;
   ull x = 0, e = 0, s = 0, f = 0, mn = INF, busy = 0, negbusy = INF, lv = 0;
   for (ull r = tid; r < tm.T; r += WG) {
-    const ull* p = reinterpret_cast<const ull*>(&a.parts[tm.id + r * a.nteams]);
+    // Group rank r is rank r % Tteam of member team r / Tteam.
+    const ull team = tm.k > 1 ? (ull)ld_agent_i32(&tc->gteam[r / tm.Tteam]) : tm.id;
+    const ull* p = reinterpret_cast<const ull*>(&a.parts[team + (r % tm.Tteam) * a.nteams]);
     x += ld_agent(p + 0);
     mn = umin(mn, ld_agent(p + 1));
     e += ld_agent(p + 2);
@@ -1712,57 +1739,169 @@ __device__ __forceinline__ T ld_system(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Serial part of a serving team's claim barrier (thread 0 of one workgroup):
-// publish the request the team finished (its row and checksum first, then
-// its row's completion word), then take the next ticket, wait until the host
-// has posted that request, copy it out of the ring and acknowledge it (which
-// frees its ring entry). Leaves the ticket, or SERVE_EXIT once the host has
-// closed the ring (and every posted request is taken), in tc->query. The wait
-// is bounded by idle_ticks and the abort flag.
-__device__ __noinline__ void serve_claim(const KArgs& a, TeamCtl* tc, GridCtl* gc) {
-  if (tc->pending) {
-    const ull t = tc->pending - 1, row = tc->out_row;
-    const ull h = ld_agent(&tc->hash_acc);
-    tc->hash_acc = 0;
-    tc->pending = 0;
-    __hip_atomic_store(&a.hashes[row], h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&a.done[row], t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-  }
+// Serving: requests are dispatched to groups of idle teams. The dispatcher
+// runs under a grid lock, on the thread of whichever idle team holds it: for
+// each posted request not yet taken it picks k idle teams, k the largest
+// power of two (at most group_max) such that every waiting request still
+// finds a team (k = idle teams / waiting requests, rounded down), copies the
+// request out of the ring into the leader's control block, acknowledges the
+// ring entry and writes each member's mailbox. Few requests in flight thus
+// get most of the grid each; under load every team solves its own.
+
+__device__ bool grid_lock(const KArgs& a, unsigned* lk, bool try_once) {
+  const long long t0 = wall_clock64();
   for (;;) {
-    const ull t = atom_add(&gc->next_query.v, 1ull);
-    const long long t0 = wall_clock64();
-    bool have = false;
-    for (;;) {
-      if (ld_system(a.posted) > t) {
-        have = true;
-        break;
-      }
-      if (ld_system(a.closed)) {
-        have = ld_system(a.posted) > t;  // posted is written before closed
-        break;
-      }
-      if (__hip_atomic_load(&gc->abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-      if ((ull)(wall_clock64() - t0) > a.idle_ticks) break;
-      __builtin_amdgcn_s_sleep(64);
+    unsigned expected = 0u;
+    if (__hip_atomic_compare_exchange_strong(lk, &expected, 1u, __ATOMIC_ACQUIRE, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT))
+      return true;
+    if (try_once) return false;
+    if (__hip_atomic_load(&a.grid->abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    if ((ull)(wall_clock64() - t0) > a.tlimit) {
+      __hip_atomic_store(&a.grid->abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
     }
-    if (!have) {
-      tc->query = SERVE_EXIT;
-      return;
-    }
-    const ull e = t % a.ring_cap;
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+__device__ void grid_unlock(unsigned* lk) { __hip_atomic_store(lk, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT); }
+
+// Under the lock: assign posted requests to groups of idle teams.
+__device__ __noinline__ void serve_dispatch(const KArgs& a, GridCtl* gc) {
+  if (ld_agent(&gc->closing)) return;
+  ull fm = ld_agent(&gc->free_mask);
+  while (fm) {
+    const ull nq = ld_agent(&gc->next_query.v);
+    const ull posted = ld_system(a.posted);
+    if (posted <= nq) break;
+    const ull waiting = posted - nq;
+    const ull idle = (ull)__popcll(fm);
+    ull k = idle / waiting;
+    if (k < 1) k = 1;
+    k = 1ull << (63 - __clzll((long long)k));  // a power of two
+    if (k > a.group_max) k = a.group_max;
+    const ull e = nq % a.ring_cap;
     const int32_t src = ld_system(&a.req[2 * e]);
     const uint32_t row = (uint32_t)ld_system(&a.req[2 * e + 1]);
-    __hip_atomic_store(&a.ack[e], t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-    if (src >= 0 && src < a.n && row < a.nrows) {
-      tc->src = (ull)src;
-      tc->out_row = row;
-      tc->pending = t + 1;
-      tc->query = t;
-      return;
-    }
+    __hip_atomic_store(&a.ack[e], nq + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    st_agent(&gc->next_query.v, nq + 1);
     // A malformed entry (the host checks requests before posting them) is
     // acknowledged and dropped.
+    if (src < 0 || src >= a.n || row >= a.nrows) continue;
+    const ull leader = (ull)(__ffsll((long long)fm) - 1);
+    TeamCtl* lc = a.teams + leader;
+    lc->src = (ull)src;
+    lc->out_row = row;
+    lc->pending = nq + 1;
+    lc->query = nq;
+    lc->hash_acc = 0;
+    const ull base = ld_agent(&lc->garrive.v);
+    // Every member's mailbox and the member list first, then the sequence
+    // numbers that hand the assignment over.
+    for (ull i = 0; i < k; ++i) {
+      const ull t = (ull)(__ffsll((long long)fm) - 1);
+      fm &= fm - 1;
+      lc->gteam[i] = (uint32_t)t;
+      TeamCtl* mc = a.teams + t;
+      mc->mb_leader = leader;
+      mc->mb_k = k;
+      mc->mb_idx = i;
+      mc->mb_base = base;
+      mc->mb_exit = 0;
+    }
+    for (ull i = 0; i < k; ++i) {
+      TeamCtl* mc = a.teams + lc->gteam[i];
+      __hip_atomic_store(&mc->mb_seq, ld_agent(&mc->mb_seq) + 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
+  st_agent(&gc->free_mask, fm);
+}
+
+// Serial part of a serving team's wait (thread 0 of the last workgroup of
+// the team at its own barrier): register the team as idle, dispatch, then
+// wait for its mailbox. Leaves mb_exit = 1 when the team is to leave: the
+// host closed the ring and every posted request is taken, the team waited
+// longer than the idle limit (the launch then takes no more requests: the
+// closing word is set here and in host memory), or the abort flag is up.
+__device__ __noinline__ void serve_wait(const KArgs& a, GridCtl* gc, ull me) {
+  TeamCtl* tc = a.teams + me;
+  const ull bit = 1ull << me;
+  const ull seq0 = ld_agent(&tc->mb_seq);
+  if (!grid_lock(a, &gc->lock, false)) {
+    tc->mb_exit = 1;
+    return;
+  }
+  st_agent(&gc->free_mask, ld_agent(&gc->free_mask) | bit);
+  serve_dispatch(a, gc);
+  grid_unlock(&gc->lock);
+  const long long t0 = wall_clock64();
+  for (unsigned spin = 0;; ++spin) {
+    if (__hip_atomic_load(&tc->mb_seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != seq0) return;
+    const bool aborted = __hip_atomic_load(&gc->abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    const bool idle = (ull)(wall_clock64() - t0) > a.idle_ticks;
+    const bool closed = ld_system(a.closed) != 0;
+    if (aborted || idle || closed || (spin & 7) == 0) {
+      if (grid_lock(a, &gc->lock, !(aborted || idle || closed))) {
+        if (__hip_atomic_load(&tc->mb_seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != seq0) {
+          grid_unlock(&gc->lock);
+          return;
+        }
+        serve_dispatch(a, gc);
+        bool leave = aborted;
+        if (__hip_atomic_load(&tc->mb_seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == seq0) {
+          // posted is written before closed, so once closed is seen a
+          // posted count at or below the next ticket means nothing is left.
+          if (closed && ld_system(a.posted) <= ld_agent(&gc->next_query.v)) leave = true;
+          if (ld_agent(&gc->closing)) leave = true;
+          if (idle) {
+            st_agent(&gc->closing, 1ull);
+            __hip_atomic_store(a.dev_closed, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            leave = true;
+          }
+        } else {
+          leave = false;  // assigned by the dispatch above
+        }
+        if (leave) {
+          st_agent(&gc->free_mask, ld_agent(&gc->free_mask) & ~bit);
+          tc->mb_exit = 1;
+        }
+        grid_unlock(&gc->lock);
+        if (leave || __hip_atomic_load(&tc->mb_seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != seq0) return;
+      } else if (aborted || idle || closed) {
+        // The lock wait itself gave up (abort): leave without it.
+        tc->mb_exit = 1;
+        return;
+      }
+    }
+    __builtin_amdgcn_s_sleep(32);
+  }
+}
+
+// Serial part of a serving group's last barrier for a request: its row (and
+// checksum) first, then the row's completion word, in host-visible order.
+__device__ __noinline__ void serve_publish(const KArgs& a, TeamCtl* lc) {
+  if (!lc->pending) return;
+  const ull t = lc->pending - 1, row = lc->out_row;
+  const ull h = ld_agent(&lc->hash_acc);
+  lc->hash_acc = 0;
+  lc->pending = 0;
+  __hip_atomic_store(&a.hashes[row], h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(&a.done[row], t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Point a workgroup's Team at the per-team workspace and control block of
+// team `t` (its own, or its group's leader when serving).
+__device__ __forceinline__ void bind_workspace(const KArgs& a, Team& tm, ull t) {
+  tm.id = t;
+  tm.ctl = a.teams + t;
+  tm.bitmap = a.bitmap + t * a.nwords;
+  tm.hint = a.hint ? a.hint + t * (ull)a.n : nullptr;
+  tm.key1 = a.key1 ? a.key1 + t * a.nwords : nullptr;
+  tm.key2 = a.key1 ? a.key2 + t * a.n2 : nullptr;
+  tm.H = a.H + t * 2 * a.hcap;
+  tm.L = a.L + t * 2 * a.lcap;
+  tm.samples = a.samples + t * a.probe_cap;
 }
 
 // ---------------------------------------------------------------------------
@@ -1778,21 +1917,22 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
   const unsigned xcc = __builtin_amdgcn_s_getreg(20 | (15 << 11)) & (MAX_XCC - 1);  // hwreg XCC_ID
 
   Team tm;
-  tm.id = b % a.nteams;
-  tm.rank = b / a.nteams;
-  tm.T = a.G / a.nteams;
-  tm.ctl = a.teams + tm.id;
-  tm.bitmap = a.bitmap + tm.id * a.nwords;
-  tm.hint = a.hint ? a.hint + tm.id * (ull)a.n : nullptr;
-  tm.key1 = a.key1 ? a.key1 + tm.id * a.nwords : nullptr;
-  tm.key2 = a.key1 ? a.key2 + tm.id * a.n2 : nullptr;
-  tm.H = a.H + tm.id * 2 * a.hcap;
-  tm.L = a.L + tm.id * 2 * a.lcap;
-  tm.samples = a.samples + tm.id * a.probe_cap;
+  const ull own_rank = b / a.nteams;
+  tm.own = b % a.nteams;
+  tm.rank = own_rank;
+  tm.Tteam = a.G / a.nteams;
+  tm.T = tm.Tteam;
+  tm.k = 1;
+  bind_workspace(a, tm, tm.own);
   tm.Fb = a.F + b * a.segcap;
   tm.FDb = a.FD + b * a.segcap;
   tm.epoch = 0;
-  ull* dist = a.dist_int ? a.dist_int + tm.id * n : nullptr;
+  tm.l2_epoch = 0;
+  tm.l2_base = 0;
+  ull* dist = nullptr;
+  // Serving with several teams: each request is solved by a group of teams
+  // (see serve_dispatch); a team alone meets on its own barrier only.
+  const bool grouped = a.serve && a.nteams > 1;
 
   // Phase clock: the team's first workgroup reads the wall clock as it
   // leaves each barrier.
@@ -1843,28 +1983,48 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
   ph0 += lap();
 
   for (;;) {
-    // Take the next source (serving: publish the finished request, then wait
-    // for the next one).
-    auto claim = [&]() {
-      if (tid != 0) return;
-      if (a.serve) {
-        serve_claim(a, tm.ctl, gc);
-      } else {
-        tm.ctl->query = (a.cancel && ld_agent(&gc->cancelled)) ? (ull)a.n_src : atom_add(&gc->next_query.v, 1ull);
-      }
-    };
+    ull qi;
     if (a.serve) {
-      // The finished row must be visible outside the device (system scope)
-      // before the claim publishes it.
-      __builtin_amdgcn_s_waitcnt(0);
+      // Serving: this team alone becomes idle and waits for its next
+      // assignment, then joins its group (leader's workspace, group ranks).
+      if (grouped) {
+        tm.l2_arrive = nullptr;
+        tm.l2_gen = nullptr;
+        tm.l2_size = 0;
+      }
+      auto wait = [&]() {
+        if (tid == 0) serve_wait(a, gc, tm.own);
+      };
+      if (!team_sync(a, sh, tm, wait)) return;
+      const TeamCtl* mine = a.teams + tm.own;
+      if (ld_agent(&mine->mb_exit)) break;
+      const ull leader = ld_agent(&mine->mb_leader);
+      tm.k = ld_agent(&mine->mb_k);
+      tm.T = tm.k * tm.Tteam;
+      tm.rank = ld_agent(&mine->mb_idx) * tm.Tteam + own_rank;
+      bind_workspace(a, tm, leader);
+      if (grouped && tm.k > 1) {
+        tm.l2_arrive = &tm.ctl->garrive.v;
+        tm.l2_gen = &tm.ctl->ggen.v;
+        tm.l2_size = tm.k;
+        tm.l2_base = ld_agent(&mine->mb_base);
+        tm.l2_epoch = 0;
+      }
+      if (tid == 0) g_tm = tm;
       __syncthreads();
-      if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+      qi = ld_agent(&tm.ctl->query);
+    } else {
+      // Take the next source.
+      auto claim = [&]() {
+        if (tid == 0)
+          tm.ctl->query = (a.cancel && ld_agent(&gc->cancelled)) ? (ull)a.n_src : atom_add(&gc->next_query.v, 1ull);
+      };
+      if (!team_sync(a, sh, tm, claim)) return;
+      qi = ld_agent(&tm.ctl->query);
+      if (qi >= (ull)a.n_src) break;
     }
-    if (!team_sync(a, sh, tm, claim)) return;
-    const ull qi = ld_agent(&tm.ctl->query);
-    if (a.serve ? qi == SERVE_EXIT : qi >= (ull)a.n_src) break;
     ull* out = a.dist_out + (a.serve ? ld_agent(&tm.ctl->out_row) : qi) * n;
-    if (!a.dist_int) dist = out;
+    dist = a.dist_int ? a.dist_int + tm.id * n : out;
 
     // S0: delta = inf, Q empty; then delta[s] = 0 and Update(s).
     for (ull i = tm.rank * WG + tid; i < n; i += tm.T * WG) dist[i] = INF;
@@ -2033,12 +2193,24 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
       h = wave_sum(h);
       if (lane_id() == 0) atom_add(&tm.ctl->hash_acc, h);
     }
+    if (a.serve) {
+      // The group's last barrier for this request publishes it; the row must
+      // be visible outside the device (system scope) first.
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+      auto publish = [&]() {
+        if (tid == 0) serve_publish(a, tm.ctl);
+      };
+      if (!team_sync(a, sh, tm, publish)) return;
+    }
   }
-  if (tm.rank == 0 && tid == 0) {
-    tm.ctl->phase_ticks[0] += ph0;
-    tm.ctl->phase_ticks[1] += ph1;
-    tm.ctl->phase_ticks[2] += ph2;
-    tm.ctl->phase_ticks[3] += ph3;
+  if (own_rank == 0 && tid == 0) {
+    TeamCtl* pc = a.teams + tm.own;
+    pc->phase_ticks[0] += ph0;
+    pc->phase_ticks[1] += ph1;
+    pc->phase_ticks[2] += ph2;
+    pc->phase_ticks[3] += ph3;
   }
 }
 
@@ -2559,12 +2731,13 @@ struct sssp_server {
   Launch L;
   uint64_t n = 0, rows = 0, cap = 0;
   // Ring and completion words in pinned, coherent host memory, shared with
-  // the kernel: req[cap] pairs, then posted, closed, ack[cap], done[rows],
-  // hashes[rows].
+  // the kernel: req[cap] pairs, then posted, closed | dev_closed, ack[cap],
+  // done[rows], hashes[rows].
   int32_t* req = nullptr;
   uint64_t* words = nullptr;
   uint64_t* posted = nullptr;
   uint32_t* closed = nullptr;
+  uint32_t* dev_closed = nullptr;  // set by the kernel once it takes no more requests
   uint64_t* ack = nullptr;
   uint64_t* done = nullptr;
   uint64_t* hashes = nullptr;
@@ -2575,6 +2748,18 @@ struct sssp_server {
   bool stopped = false;
   sssp_status stop_status = SSSP_OK;
   sssp_stats final_stats{};
+  // Admission by memory budget (sssp_server_start_budget): the result rows
+  // are the library's, drawn from the budget; requests wait in `waitq` until
+  // a row is free, and a finished request holds its row until released.
+  bool budget = false;
+  DevBuf own_rows;
+  uint64_t budget_bytes = 0;
+  uint64_t ws_bytes = 0;                // workspace counted in the budget
+  std::deque<int32_t> waitq;            // sources of requests not yet admitted, in ticket order
+  uint64_t next_enqueue = 0;            // ticket of the next enqueued request
+  std::vector<uint32_t> free_rows;
+  std::unordered_map<uint64_t, uint32_t> held;  // finished, not yet released: ticket -> row
+  std::unordered_map<uint64_t, uint32_t> admitted_row;  // admitted, not finished: ticket -> row
 };
 
 extern "C" {
@@ -2784,59 +2969,38 @@ sssp_status sssp_row_hash(const uint64_t* dist, int64_t n, void* stream, uint64_
   return SSSP_OK;
 }
 
-sssp_status sssp_server_start(const sssp_graph* gc, const sssp_params* params, uint64_t* dist_rows, uint32_t rows,
-                              uint32_t ring_capacity, uint32_t flags, uint32_t idle_ms, void* stream,
-                              sssp_server** out) {
-  last_error().clear();
-  if (!out) return fail(SSSP_ERR_INVALID_ARGUMENT, "out is NULL");
-  *out = nullptr;
-  if (!gc || !dist_rows || rows == 0 || ring_capacity == 0)
-    return fail(SSSP_ERR_INVALID_ARGUMENT, "graph or dist_rows is NULL, or rows / ring_capacity is 0");
-  if (flags & ~SSSP_SERVE_HASH) return fail(SSSP_ERR_INVALID_ARGUMENT, "unknown server flags");
-  if (gc->serving) return fail(SSSP_ERR_INVALID_ARGUMENT, "a server is already running on this graph");
-  if (gc->pending) return fail(SSSP_ERR_INVALID_ARGUMENT, "an asynchronous solve is pending on this graph");
-  sssp_graph* g = const_cast<sssp_graph*>(gc);
-  sssp_server* s = new (std::nothrow) sssp_server;
-  if (!s) return fail(SSSP_ERR_OUT_OF_MEMORY, "server");
-  sssp_status ps = check_params(params, s->L.p, s->L.tu);
-  if (ps != SSSP_OK) {
-    delete s;
-    return ps;
-  }
+}  // extern "C"
+
+namespace {
+
+// Start a serving launch into `dist_rows` (rows x n); `s` is filled in and
+// owned by the caller of this helper (freed with destroy_server on error).
+sssp_status launch_server(sssp_graph* g, sssp_server* s, uint64_t* dist_rows, uint32_t rows, uint32_t ring_capacity,
+                          uint32_t flags, uint32_t idle_ms) {
   // Half the co-resident slots by default, leaving room for other kernels
   // (copies, checksums, a second server).
   if (!s->L.p.tuning || s->L.p.tuning->blocks_per_cu == 0) s->L.tu.blocks_per_cu = 2;
-  if (s->L.p.trace || s->L.p.extract_counts || s->L.p.max_steps) {
-    delete s;
+  if (s->L.p.trace || s->L.p.extract_counts || s->L.p.max_steps)
     return fail(SSSP_ERR_INVALID_ARGUMENT, "trace, extract_counts and max_steps are not available when serving");
-  }
   s->g = g;
-  s->caller = (hipStream_t)stream;
   s->n = (uint64_t)g->n;
   s->rows = rows;
   s->cap = ring_capacity;
   s->row_ticket.assign(rows, 0);
-  auto cleanup = [&](sssp_status st) {
-    if (s->req) (void)hipHostFree(s->req);
-    if (s->words) (void)hipHostFree(s->words);
-    if (s->st) (void)hipStreamDestroy(s->st);
-    if (s->ev0) (void)hipEventDestroy(s->ev0);
-    if (s->ev1) (void)hipEventDestroy(s->ev1);
-    delete s;
-    return st;
-  };
   {
     int occ = 0;
     hipError_t e = hipSetDevice(g->device);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, stepping_kernel, WG, 0);
-    if (e != hipSuccess) return cleanup(fail(from_hip(e), hipGetErrorString(e)));
+    if (e != hipSuccess) return fail(from_hip(e), hipGetErrorString(e));
     const uint32_t G = std::max(1u, std::min<uint32_t>(s->L.tu.blocks_per_cu, (uint32_t)std::max(occ, 1))) *
                        (uint32_t)g->cus;
-    // Default: teams of 16 workgroups (a power of two count, at least 8).
+    // Default: teams of 16 workgroups (a power of two count, at least 8),
+    // at most 64 (the dispatcher's idle-team mask).
     uint32_t t = 8;
-    while (t * 2 <= G / 16 && G % (t * 2) == 0) t *= 2;
+    while (t * 2 <= G / 16 && t * 2 <= 64 && G % (t * 2) == 0) t *= 2;
     sssp_status ls = prepare_launch(g, s->L, G % 8 == 0 ? t : 1, dist_rows, s->caller);
-    if (ls != SSSP_OK) return cleanup(ls);
+    if (ls != SSSP_OK) return ls;
+    if (s->L.nteams > 64) return fail(SSSP_ERR_INVALID_ARGUMENT, "a server runs at most 64 teams");
   }
   {
     // HIP spreads streams over a few shared hardware queues, and a queue runs
@@ -2851,7 +3015,7 @@ sssp_status sssp_server_start(const sssp_graph* gc, const sssp_params* params, u
     if (e == hipSuccess) e = hipEventRecord(ready, s->caller);
     if (e == hipSuccess) e = hipStreamWaitEvent(s->st, ready, 0);
     if (ready) (void)hipEventDestroy(ready);
-    if (e != hipSuccess) return cleanup(fail(from_hip(e), std::string("server stream: ") + hipGetErrorString(e)));
+    if (e != hipSuccess) return fail(from_hip(e), std::string("server stream: ") + hipGetErrorString(e));
   }
   // Host ring: requests, then the control words, in one coherent pinned
   // allocation (device loads and stores reach it directly).
@@ -2861,12 +3025,13 @@ sssp_status sssp_server_start(const sssp_graph* gc, const sssp_params* params, u
     if (e == hipSuccess) e = hipHostMalloc((void**)&s->words, words * 8, hipHostMallocCoherent);
     if (e == hipSuccess) e = hipEventCreate(&s->ev0);
     if (e == hipSuccess) e = hipEventCreate(&s->ev1);
-    if (e != hipSuccess) return cleanup(fail(from_hip(e), std::string("server ring: ") + hipGetErrorString(e)));
+    if (e != hipSuccess) return fail(from_hip(e), std::string("server ring: ") + hipGetErrorString(e));
   }
   std::memset(s->req, 0, req_bytes);
   std::memset(s->words, 0, words * 8);
   s->posted = s->words;
   s->closed = reinterpret_cast<uint32_t*>(s->words + 1);
+  s->dev_closed = s->closed + 1;
   s->ack = s->words + 2;
   s->done = s->ack + s->cap;
   s->hashes = s->done + rows;
@@ -2878,13 +3043,20 @@ sssp_status sssp_server_start(const sssp_graph* gc, const sssp_params* params, u
   a.req = s->req;
   a.posted = s->posted;
   a.closed = s->closed;
+  a.dev_closed = s->dev_closed;
   a.ack = s->ack;
   a.done = s->done;
   a.hashes = s->hashes;
   a.ring_cap = s->cap;
   a.nrows = rows;
+  {
+    uint32_t gm = s->L.tu.group_max ? std::min(s->L.tu.group_max, s->L.nteams) : s->L.nteams;
+    uint32_t p2 = 1;
+    while (p2 * 2 <= gm) p2 *= 2;
+    a.group_max = p2;
+  }
   a.idle_ticks = g->tick_khz * (uint64_t)(idle_ms ? idle_ms : 60000);
-  a.tlimit += a.idle_ticks;  // team members wait at the claim barrier while a request is awaited
+  a.tlimit += a.idle_ticks;  // team members wait at their barrier while a request is awaited
   hipError_t e = stage_launch(g, s->L, s->st);
   if (e == hipSuccess) e = hipEventRecord(s->ev0, s->st);
   if (e == hipSuccess) {
@@ -2897,27 +3069,39 @@ sssp_status sssp_server_start(const sssp_graph* gc, const sssp_params* params, u
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipEventRecord(s->ev1, s->st);
-  if (e != hipSuccess) return cleanup(fail(from_hip(e), std::string("server launch: ") + hipGetErrorString(e)));
+  if (e != hipSuccess) return fail(from_hip(e), std::string("server launch: ") + hipGetErrorString(e));
   g->serving = true;
-  *out = s;
   return SSSP_OK;
 }
 
-sssp_status sssp_server_submit(sssp_server* s, int32_t source, uint32_t row, uint64_t* ticket) {
-  last_error().clear();
-  if (!s) return fail(SSSP_ERR_INVALID_ARGUMENT, "server is NULL");
-  if (s->stopped) return fail(SSSP_ERR_INVALID_ARGUMENT, "server is stopped");
-  if (source < 0 || (uint64_t)source >= s->n)
-    return fail(SSSP_ERR_INVALID_ARGUMENT, "source " + std::to_string(source) + " out of range");
-  if (row >= s->rows) return fail(SSSP_ERR_INVALID_ARGUMENT, "row " + std::to_string(row) + " out of range");
-  if (s->row_ticket[row]) return fail(SSSP_ERR_INVALID_ARGUMENT, "row " + std::to_string(row) + " is busy");
+// Release what launch_server (or the budget start) acquired; the launch must
+// have ended or never started.
+void free_server(sssp_server* s) {
+  if (s->req) (void)hipHostFree(s->req);
+  if (s->words) (void)hipHostFree(s->words);
+  if (s->st) (void)hipStreamDestroy(s->st);
+  if (s->ev0) (void)hipEventDestroy(s->ev0);
+  if (s->ev1) (void)hipEventDestroy(s->ev1);
+  s->own_rows.release(nullptr);
+  delete s;
+}
+
+sssp_status start_checks(const sssp_graph* gc, uint32_t flags) {
+  if (flags & ~SSSP_SERVE_HASH) return fail(SSSP_ERR_INVALID_ARGUMENT, "unknown server flags");
+  if (gc->serving) return fail(SSSP_ERR_INVALID_ARGUMENT, "a server is already running on this graph");
+  if (gc->pending) return fail(SSSP_ERR_INVALID_ARGUMENT, "an asynchronous solve is pending on this graph");
+  return SSSP_OK;
+}
+
+// Post one request into the ring (the caller has checked source and row).
+sssp_status post_request(sssp_server* s, int32_t source, uint32_t row, uint64_t* ticket) {
   const uint64_t t = s->next_ticket;
   const uint64_t e = t % s->cap;
   // The entry is free once the kernel has taken the request that held it.
   if (t >= s->cap && __atomic_load_n(&s->ack[e], __ATOMIC_ACQUIRE) != t - s->cap + 1)
     return fail(SSSP_ERR_INVALID_ARGUMENT, "ring full");
-  if (hipEventQuery(s->ev1) == hipSuccess)
-    return fail(SSSP_ERR_DEVICE, "the server launch has ended (idle limit reached or an error)");
+  if (__atomic_load_n(s->dev_closed, __ATOMIC_ACQUIRE) || hipEventQuery(s->ev1) == hipSuccess)
+    return fail(SSSP_ERR_DEVICE, "the server launch takes no more requests (idle limit reached or an error)");
   ++s->next_ticket;
   s->req[2 * e] = source;
   s->req[2 * e + 1] = (int32_t)row;
@@ -2926,6 +3110,141 @@ sssp_status sssp_server_submit(sssp_server* s, int32_t source, uint32_t row, uin
   s->busy_rows.push_back(row);
   if (ticket) *ticket = t;
   return SSSP_OK;
+}
+
+// Budget servers: admit waiting requests while rows are free.
+sssp_status admit_waiting(sssp_server* s) {
+  while (!s->waitq.empty() && !s->free_rows.empty()) {
+    const uint32_t row = s->free_rows.back();
+    uint64_t t = 0;
+    sssp_status st = post_request(s, s->waitq.front(), row, &t);
+    if (st != SSSP_OK) return st;
+    s->free_rows.pop_back();
+    s->waitq.pop_front();
+    s->admitted_row[t] = row;
+  }
+  return SSSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sssp_status sssp_server_start(const sssp_graph* gc, const sssp_params* params, uint64_t* dist_rows, uint32_t rows,
+                              uint32_t ring_capacity, uint32_t flags, uint32_t idle_ms, void* stream,
+                              sssp_server** out) {
+  last_error().clear();
+  if (!out) return fail(SSSP_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (!gc || !dist_rows || rows == 0 || ring_capacity == 0)
+    return fail(SSSP_ERR_INVALID_ARGUMENT, "graph or dist_rows is NULL, or rows / ring_capacity is 0");
+  sssp_status cs = start_checks(gc, flags);
+  if (cs != SSSP_OK) return cs;
+  sssp_server* s = new (std::nothrow) sssp_server;
+  if (!s) return fail(SSSP_ERR_OUT_OF_MEMORY, "server");
+  sssp_status ps = check_params(params, s->L.p, s->L.tu);
+  if (ps == SSSP_OK) {
+    s->caller = (hipStream_t)stream;
+    ps = launch_server(const_cast<sssp_graph*>(gc), s, dist_rows, rows, ring_capacity, flags, idle_ms);
+  }
+  if (ps != SSSP_OK) {
+    free_server(s);
+    return ps;
+  }
+  *out = s;
+  return SSSP_OK;
+}
+
+sssp_status sssp_server_start_budget(const sssp_graph* gc, const sssp_params* params, uint64_t budget_bytes,
+                                     uint32_t flags, uint32_t idle_ms, void* stream, sssp_server** out) {
+  last_error().clear();
+  if (!out) return fail(SSSP_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (!gc) return fail(SSSP_ERR_INVALID_ARGUMENT, "graph is NULL");
+  sssp_status cs = start_checks(gc, flags);
+  if (cs != SSSP_OK) return cs;
+  sssp_graph* g = const_cast<sssp_graph*>(gc);
+  sssp_server* s = new (std::nothrow) sssp_server;
+  if (!s) return fail(SSSP_ERR_OUT_OF_MEMORY, "server");
+  s->budget = true;
+  s->budget_bytes = budget_bytes;
+  s->caller = (hipStream_t)stream;
+  sssp_status ps = check_params(params, s->L.p, s->L.tu);
+  if (ps == SSSP_OK && (!s->L.p.tuning || s->L.p.tuning->blocks_per_cu == 0)) s->L.tu.blocks_per_cu = 2;
+  uint64_t rows = 0;
+  if (ps == SSSP_OK) {
+    // The workspace of the launch comes out of the budget first; the rest is
+    // result rows of 8 n bytes.
+    Launch probe;
+    probe.p = s->L.p;
+    probe.tu = s->L.tu;
+    int occ = 0;
+    hipError_t e = hipSetDevice(g->device);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, stepping_kernel, WG, 0);
+    if (e != hipSuccess) {
+      ps = fail(from_hip(e), hipGetErrorString(e));
+    } else {
+      const uint32_t G = std::max(1u, std::min<uint32_t>(probe.tu.blocks_per_cu, (uint32_t)std::max(occ, 1))) *
+                         (uint32_t)g->cus;
+      uint32_t t = 8;
+      while (t * 2 <= G / 16 && t * 2 <= 64 && G % (t * 2) == 0) t *= 2;
+      ps = plan_launch(g, probe, G % 8 == 0 ? t : 1);
+      if (ps == SSSP_OK) {
+        uint64_t sz[15], ws = 0;
+        workspace_sizes(g, probe.tu, probe.geo, 0, sz);
+        for (uint64_t b : sz) ws += b;
+        s->ws_bytes = ws;
+        const uint64_t row_bytes = 8ull * (uint64_t)g->n;
+        rows = budget_bytes > ws ? (budget_bytes - ws) / row_bytes : 0;
+        if (rows == 0)
+          ps = fail(SSSP_ERR_OUT_OF_MEMORY, "budget of " + std::to_string(budget_bytes) +
+                                                " bytes holds no result row: the workspace takes " +
+                                                std::to_string(ws) + " and a row " + std::to_string(row_bytes));
+        rows = std::min<uint64_t>(rows, 1u << 16);
+      }
+    }
+  }
+  if (ps == SSSP_OK) {
+    const hipError_t e = s->own_rows.alloc(rows * 8ull * (uint64_t)g->n, s->caller);
+    if (e != hipSuccess) ps = fail(from_hip(e), std::string("server rows: ") + hipGetErrorString(e));
+  }
+  if (ps == SSSP_OK)
+    ps = launch_server(g, s, (uint64_t*)s->own_rows.p, (uint32_t)rows, (uint32_t)rows, flags, idle_ms);
+  if (ps != SSSP_OK) {
+    if (s->st) (void)hipStreamSynchronize(s->st);
+    free_server(s);
+    return ps;
+  }
+  for (uint32_t r = (uint32_t)rows; r > 0; --r) s->free_rows.push_back(r - 1);
+  *out = s;
+  return SSSP_OK;
+}
+
+sssp_status sssp_server_submit(sssp_server* s, int32_t source, uint32_t row, uint64_t* ticket) {
+  last_error().clear();
+  if (!s) return fail(SSSP_ERR_INVALID_ARGUMENT, "server is NULL");
+  if (s->budget) return fail(SSSP_ERR_INVALID_ARGUMENT, "a budget server takes requests by sssp_server_enqueue");
+  if (s->stopped) return fail(SSSP_ERR_INVALID_ARGUMENT, "server is stopped");
+  if (source < 0 || (uint64_t)source >= s->n)
+    return fail(SSSP_ERR_INVALID_ARGUMENT, "source " + std::to_string(source) + " out of range");
+  if (row >= s->rows) return fail(SSSP_ERR_INVALID_ARGUMENT, "row " + std::to_string(row) + " out of range");
+  if (s->row_ticket[row]) return fail(SSSP_ERR_INVALID_ARGUMENT, "row " + std::to_string(row) + " is busy");
+  return post_request(s, source, row, ticket);
+}
+
+sssp_status sssp_server_enqueue(sssp_server* s, int32_t source, uint64_t* ticket) {
+  last_error().clear();
+  if (!s) return fail(SSSP_ERR_INVALID_ARGUMENT, "server is NULL");
+  if (!s->budget) return fail(SSSP_ERR_INVALID_ARGUMENT, "sssp_server_enqueue needs a budget server");
+  if (s->stopped) return fail(SSSP_ERR_INVALID_ARGUMENT, "server is stopped");
+  if (source < 0 || (uint64_t)source >= s->n)
+    return fail(SSSP_ERR_INVALID_ARGUMENT, "source " + std::to_string(source) + " out of range");
+  if (__atomic_load_n(s->dev_closed, __ATOMIC_ACQUIRE) || hipEventQuery(s->ev1) == hipSuccess)
+    return fail(SSSP_ERR_DEVICE, "the server launch takes no more requests (idle limit reached or an error)");
+  s->waitq.push_back(source);
+  if (ticket) *ticket = s->next_enqueue;
+  ++s->next_enqueue;
+  return admit_waiting(s);
 }
 
 sssp_status sssp_server_poll(sssp_server* s, uint64_t* tickets, uint64_t* hashes, uint32_t max, uint32_t* count) {
@@ -2942,11 +3261,80 @@ sssp_status sssp_server_poll(sssp_server* s, uint64_t* tickets, uint64_t* hashes
       s->row_ticket[row] = 0;
       s->busy_rows[i] = s->busy_rows.back();
       s->busy_rows.pop_back();
+      if (s->budget) {
+        s->admitted_row.erase(t1 - 1);
+        s->held[t1 - 1] = row;
+      }
     } else {
       ++i;
     }
   }
   *count = c;
+  // Requests can no longer finish once the launch has ended: say so rather
+  // than leave the caller waiting.
+  if (c == 0 && (!s->busy_rows.empty() || !s->waitq.empty()) && !s->stopped &&
+      hipEventQuery(s->ev1) == hipSuccess) {
+    // Completion words written just before the end are read once more.
+    for (uint32_t row : s->busy_rows)
+      if (__atomic_load_n(&s->done[row], __ATOMIC_ACQUIRE) == s->row_ticket[row])
+        return SSSP_OK;
+    return fail(SSSP_ERR_DEVICE, "the server launch has ended with " +
+                                     std::to_string(s->busy_rows.size() + s->waitq.size()) +
+                                     " requests unfinished (idle limit reached or an error)");
+  }
+  return SSSP_OK;
+}
+
+sssp_status sssp_server_result(sssp_server* s, uint64_t ticket, const uint64_t** row) {
+  last_error().clear();
+  if (!s || !row) return fail(SSSP_ERR_INVALID_ARGUMENT, "server or row is NULL");
+  if (!s->budget) return fail(SSSP_ERR_INVALID_ARGUMENT, "sssp_server_result needs a budget server");
+  auto it = s->held.find(ticket);
+  if (it == s->held.end())
+    return fail(SSSP_ERR_INVALID_ARGUMENT, "ticket " + std::to_string(ticket) + " is not finished and held");
+  *row = (const uint64_t*)s->own_rows.p + (uint64_t)it->second * s->n;
+  return SSSP_OK;
+}
+
+sssp_status sssp_server_release(sssp_server* s, uint64_t ticket) {
+  last_error().clear();
+  if (!s) return fail(SSSP_ERR_INVALID_ARGUMENT, "server is NULL");
+  if (!s->budget) return fail(SSSP_ERR_INVALID_ARGUMENT, "sssp_server_release needs a budget server");
+  auto it = s->held.find(ticket);
+  if (it == s->held.end())
+    return fail(SSSP_ERR_INVALID_ARGUMENT, "ticket " + std::to_string(ticket) + " is not finished and held");
+  s->free_rows.push_back(it->second);
+  s->held.erase(it);
+  if (s->stopped) return SSSP_OK;
+  return admit_waiting(s);
+}
+
+sssp_status sssp_server_take(sssp_server* s, uint64_t ticket, uint64_t* dst, void* stream) {
+  last_error().clear();
+  if (!dst) return fail(SSSP_ERR_INVALID_ARGUMENT, "dst is NULL");
+  const uint64_t* row = nullptr;
+  sssp_status rs = sssp_server_result(s, ticket, &row);
+  if (rs != SSSP_OK) return rs;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(dst, row, 8ull * s->n, hipMemcpyDefault, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(from_hip(e), std::string("server take: ") + hipGetErrorString(e));
+  return sssp_server_release(s, ticket);
+}
+
+sssp_status sssp_server_counts(const sssp_server* s, sssp_server_load* load) {
+  last_error().clear();
+  if (!s || !load) return fail(SSSP_ERR_INVALID_ARGUMENT, "server or load is NULL");
+  std::memset(load, 0, sizeof(*load));
+  load->rows = s->rows;
+  load->row_bytes = 8ull * s->n;
+  load->budget_bytes = s->budget_bytes;
+  load->teams = s->L.nteams;
+  load->waiting = s->waitq.size();
+  load->admitted = s->busy_rows.size();
+  load->held = s->budget ? s->held.size() : 0;
+  load->free_rows = s->budget ? s->free_rows.size() : s->rows - s->busy_rows.size();
+  load->workspace_bytes = s->budget ? s->ws_bytes : (s->g ? s->g->workspace_bytes() : 0);
   return SSSP_OK;
 }
 
@@ -2970,6 +3358,8 @@ sssp_status sssp_server_stop(sssp_server* s, sssp_stats* stats) {
       if (s->stop_status == SSSP_OK && aborted)
         s->stop_status = fail(SSSP_ERR_DEVICE, "server barrier or request wait timed out");
     }
+    // Requests never admitted are dropped.
+    s->waitq.clear();
     s->g->serving = false;
   }
   if (stats) *stats = s->final_stats;
@@ -2980,12 +3370,7 @@ sssp_status sssp_server_destroy(sssp_server* s) {
   if (!s) return SSSP_OK;
   sssp_status st = SSSP_OK;
   if (!s->stopped) st = sssp_server_stop(s, nullptr);
-  (void)hipHostFree(s->req);
-  (void)hipHostFree(s->words);
-  (void)hipStreamDestroy(s->st);
-  (void)hipEventDestroy(s->ev0);
-  (void)hipEventDestroy(s->ev1);
-  delete s;
+  free_server(s);
   return st;
 }
 

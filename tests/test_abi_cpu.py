@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header(tmp_path):
     # Compile a probe against the header with the host C compiler and compare
     # every field offset and struct size with the ctypes mirror.
-    structs = [N.sssp_tuning, N.sssp_step_record, N.sssp_params, N.sssp_stats]
+    structs = [N.sssp_tuning, N.sssp_step_record, N.sssp_params, N.sssp_stats, N.sssp_server_load]
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "%s"' % HEADER, "int main(void) {"]
     for S in structs:
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (S.__name__, S.__name__))
@@ -147,6 +147,16 @@ def test_serving_and_checksum_null_arguments():
     h = ctypes.c_uint64()
     assert lib.sssp_row_hash(None, 5, None, ctypes.byref(h)) == N.SSSP_ERR_INVALID_ARGUMENT
     assert "NULL" in N.sssp_last_error()
+    assert lib.sssp_server_start_budget(None, ctypes.byref(p), 1 << 30, 0, 0, None,
+                                        ctypes.byref(s)) == N.SSSP_ERR_INVALID_ARGUMENT
+    assert not s.value
+    assert lib.sssp_server_enqueue(None, 0, ctypes.byref(t)) == N.SSSP_ERR_INVALID_ARGUMENT
+    r = ctypes.c_void_p()
+    assert lib.sssp_server_result(None, 0, ctypes.byref(r)) == N.SSSP_ERR_INVALID_ARGUMENT
+    assert lib.sssp_server_release(None, 0) == N.SSSP_ERR_INVALID_ARGUMENT
+    assert lib.sssp_server_take(None, 0, None, None) == N.SSSP_ERR_INVALID_ARGUMENT
+    ld = N.sssp_server_load()
+    assert lib.sssp_server_counts(None, ctypes.byref(ld)) == N.SSSP_ERR_INVALID_ARGUMENT
 
 
 def test_async_solve_null_arguments():

@@ -73,7 +73,7 @@ def test_row_hash_matches_definition(sp, torch_cuda):
         assert sp.row_hash(t) == np_row_hash(d), n
 
 
-@pytest.mark.parametrize("case", ["rmat", "road", "rmat-tree"])
+@pytest.mark.parametrize("case", ["rmat", "road", "rmat-tree", "rmat-fixed-teams"])
 def test_server_matches_oracle(sp, torch_cuda, side_stream, case):
     torch = torch_cuda
     if case.startswith("rmat"):
@@ -82,6 +82,8 @@ def test_server_matches_oracle(sp, torch_cuda, side_stream, case):
         kw = dict(rule="rho", rho=2048)
         if case == "rmat-tree":
             kw["tuning"] = {"queue": 1}  # tournament-tree LaB-PQ (Sec. 4.2)
+        if case == "rmat-fixed-teams":
+            kw["tuning"] = {"group_max": 1}  # one team per request
     else:
         g = graphgen.road(70, 70, seed=42)
         G = sp.Graph.from_csr(g.offsets, g.targets, g.weights, reorder=False)
@@ -192,7 +194,8 @@ def test_server_errors_and_idle_limit(sp, torch_cuda, side_stream):
     S.close()
     d, _ = sp.solve(G, [0])  # usable again
     assert np.array_equal(sp.to_numpy_u64(d)[0], oracle.dijkstra(g.offsets, g.targets, g.weights, 0))
-    # A server whose teams wait longer than idle_ms for work ends by itself.
+    # A server whose teams wait longer than idle_ms for work takes no more
+    # requests and ends by itself.
     S = sp.Server(G, rows, rule="bf", idle_ms=100)
     time.sleep(1.0)
     with pytest.raises(sp.SSSPError) as ei:
