@@ -4,25 +4,32 @@ One "step" of this benchmark is one whole solve of the hot path (init,
 then ExtDist -> Extract -> Relax/WriteMin -> Update until the queue is
 empty). The default workload is the power-law graph: R-MAT scale 24, edge
 factor 16 (a = 0.57, b = 0.19, c = 0.19), symmetrised and deduplicated,
-weights uniform in [1, 2^18), one source in the largest component,
-rho-stepping. The graph is resident in HBM before timing starts.
+weights uniform in [1, 2^18), ten seeded sources in the largest component,
+rho-stepping. The graph is resident in HBM before timing starts. rho is
+swept over 2^16 .. 2^22 first (one solve per source each; `rho_sweep`) and
+the K timed solves use the fastest.
 
-The default line also carries `latency`: a short serving run (R-MAT scale 22
-and a 2000x2000 road grid resident, Poisson arrivals) with p50/p99 of the
-serving launches against a one-query-at-a-time loop (`--latency-queries 0`
-skips it).
+The default line also carries the metric's other workloads, each under its
+own key: `road_delta_sweep` (the 5000 x 5000 road grid, Delta*-stepping with
+Delta = 2^10 .. 2^16 and Bellman-Ford: time, steps, time per step),
+`knn_batched` (a 10-NN graph of 10^7 points, 64 queries in one launch
+against the same queries one launch each) and `latency` (a short serving
+run: R-MAT scale 22 and a 2000 x 2000 road grid resident, Poisson arrivals,
+p50/p99 of the serving launches against a one-query-at-a-time loop);
+`--extras` selects them.
 
-`--workload knn10000` times the many-query workload instead: a 10-NN graph
-of 10^7 points in 1000 Gaussian clusters and 64 sources, all solved in one
-launch (a step = one batch of 64 queries), next to the same 64 queries
-solved one launch at a time. `--workload serve` runs the serving comparison
-at full length; `road5000` and `grid256` time single solves.
+`--workload knn10000` times the many-query workload alone (with an optional
+parameter search); `--workload serve` runs the serving comparison at full
+length (a closed loop over a prefix of the trace for the saturation rates,
+then the open loop over the whole trace); `road5000` and `grid256` time
+single solves.
 
 Prints one JSON line. `value` is edges relaxed per second (GTEPS, counting
-repeated relaxations) over the K timed steps; `roofline` prices the
-algorithmic bytes of the stepping kernel against the 8 TB/s HBM peak;
-`cpu_baseline` times the CPU oracle (single-threaded binary-heap Dijkstra)
-on the same graph and sources.
+repeated relaxations) over the K timed steps, `gteps_useful` arcs out of
+reachable vertices per second; `roofline` prices the algorithmic bytes of
+the stepping kernel against the 8 TB/s HBM peak; `cpu_baseline` times the
+CPU oracle (single-threaded binary-heap Dijkstra, median of 3) on the same
+graph.
 """
 
 from __future__ import annotations
@@ -42,7 +49,7 @@ sys.path.insert(0, REPO)
 METRIC = "edges relaxed/s (GTEPS) + % HBM roofline; p50/p99 query latency batched vs plain"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRCS = [os.path.join(REPO, "paper_2105_06145_amd", "csrc", f)
-               for f in ("stepping.hip", "graph.hip", "internal.h")]
+               for f in ("stepping.hip", "graph.hip", "internal.h", "hint_code.h")]
 TRAFFIC_FILE = os.path.join(REPO, "profiles", "traffic_stepping_kernel_rmat24.json")
 
 WORKLOADS = {
@@ -65,21 +72,31 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(n: int, st: dict, nsrc: int, offset_bytes: int = 8, relabelled: bool = True) -> int:
-    """Bytes the method must move for one launch (nsrc solves), from its counters.
+def algorithmic_bytes(n: int, st: dict, nsrc: int, offset_bytes: int = 8) -> int:
+    """Bytes the method must move for one launch (nsrc solves), from its
+    counters, by the roofline's accounting of the path:
 
-    S0, per source: 8n (distance fill) + n/8 (bitmap clear).
-    Output in caller ids (relabelled graph), per source: 4n (id map) + 8n (read) + 8n (write).
-    Extract, bitmap step: n/8 (flag scan) + 8 q (keys of members).
-    Extract, list step:   12 q (list entry + key).
-    Explicit lists: 4 per entry written (kept and new members).
-    Per extracted vertex: 2 * offset_bytes (row bounds) + 8 (its key) + 8 (F write + read).
-    Per relaxed arc:      8 (packed target, weight) + 8 (key of the target).
-    Per successful WriteMin: 8 (key write) + 8 (flag word RMW).
+    S0, per source:        8 n (distance fill) + n / 8 (bitmap clear).
+    Dense (bitmap) steps:  n / 8 (flag scan) per step + 8 per queued member (keys).
+    Per extracted vertex:  2 * offset_bytes (row bounds) + 8 (its key) + 8 (F write + read).
+    Per relaxed arc:       8 (packed target, weight) + 8 (key of the target).
+    Per successful WriteMin: 8 (key write) + 4 (flag word); explicit-list
+                           mode: + 4 per list entry written.
     """
-    b = nsrc * (8 * n + n // 8 + (20 * n if relabelled else 0))
-    b += st["dense_steps"] * (n // 8) + 8 * st["queue_dense"] + 12 * st["queue_list"] + 4 * st["list_appends"]
-    b += (2 * offset_bytes + 16) * st["extracted"] + 16 * st["edges_relaxed"] + 16 * st["writemin_success"]
+    b = nsrc * (8 * n + n // 8)
+    b += st["dense_steps"] * (n // 8) + 8 * st["queue_dense"]
+    b += (2 * offset_bytes + 16) * st["extracted"] + 16 * st["edges_relaxed"]
+    b += 12 * st["writemin_success"] + 4 * st["list_appends"]
+    return b
+
+
+def implementation_bytes(n: int, st: dict, nsrc: int, offset_bytes: int = 8, relabelled: bool = True) -> int:
+    """The same with what this implementation adds to the method's bytes: the
+    copy of each row back to the caller's vertex ids (4 n id map + 8 n read +
+    8 n write per source on relabelled graphs), the list steps' reads of the
+    queue (4 per entry + 8 per key) and 8-byte flag words (+ 4 per success)."""
+    b = algorithmic_bytes(n, st, nsrc, offset_bytes)
+    b += nsrc * (20 * n if relabelled else 0) + 12 * st["queue_list"] + 4 * st["writemin_success"]
     return b
 
 
@@ -108,6 +125,41 @@ def roofline_entry(b_alg: int, kernel_avg_ms: float, traffic):
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "stepping_kernel",
             "algorithmic_bytes_per_launch": int(b_alg), "kernel_avg_ms": round(kernel_avg_ms, 4)}
+
+
+def host_cpu() -> dict:
+    """CPU model and core counts of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "nproc": avail, "cpu_count": os.cpu_count()}
+
+
+def oracle_baseline(g, src: int, runs: int = 3) -> dict:
+    """The oracle (single-threaded binary-heap Dijkstra) from one source,
+    timed `runs` times; the rate is arcs scanned per second of the median."""
+    import oracle
+    secs = []
+    settled = scanned = 0
+    for _ in range(runs):
+        c0 = oracle.now()
+        _, settled, scanned = oracle.dijkstra(g.offsets, g.targets, g.weights, src, stats=True)
+        secs.append(oracle.now() - c0)
+    med = float(np.median(secs))
+    return {"value": round(scanned / med / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": f"one binary-heap Dijkstra solve from the first source ({settled} vertices settled, "
+                      f"{scanned} arcs relaxed), timed {runs} times on 1 thread: median {med:.2f} s "
+                      f"(runs {', '.join(f'{x:.2f}' for x in secs)} s)",
+            **host_cpu()}
 
 
 def reachable_arcs(g, dist_row) -> int:
@@ -153,15 +205,69 @@ def stream_copy_gbs(torch, mib: int = 1024, reps: int = 5) -> float:
     return gbs
 
 
+def measure_ceilings(torch, g, relax_arcs: int, relax_ms: float) -> dict:
+    """The memory-system rates that bound Relax, measured by the ceiling
+    microbenchmarks (libsssp_ceilings.so) over tables of this graph's size:
+    random 2-byte gathers (the filter's key-bound read per arc) and random
+    64-bit atomic minima (WriteMin), with indices uniform over the vertices
+    and, separately, distributed as the graph's arc targets (a random arc's
+    target, numbered by decreasing degree as the library numbers vertices).
+    Beside them, Relax's own rate: arcs relaxed per second of Relax phase."""
+    import ctypes
+
+    from paper_2105_06145_amd import _native
+    L = _native.ceilings_lib()
+    n = g.n
+    count = 1 << 27
+    rng = np.random.default_rng(12345)
+    deg = np.diff(g.offsets)
+    order = np.argsort(-deg, kind="stable")
+    rank = np.empty(n, dtype=np.int32)
+    rank[order] = np.arange(n, dtype=np.int32)
+    arcs = rng.integers(0, g.m, count)
+    idx_deg = torch.from_numpy(rank[g.targets[arcs]]).cuda()
+    idx_uni = torch.randint(0, n, (count,), dtype=torch.int32, device="cuda")
+    del arcs, order, rank
+    t16 = torch.zeros(n, dtype=torch.int16, device="cuda")
+    t64 = torch.full((n,), (1 << 62), dtype=torch.int64, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int64, device="cuda")
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def rate(call, reps=3):
+        assert call() == 0  # warm-up
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            assert call() == 0
+        e1.record()
+        torch.cuda.synchronize()
+        return round(count * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 2)
+
+    vp = ctypes.c_void_p
+    out = {"unit": "G accesses/s", "accesses_per_launch": count, "table_entries": n}
+    for name, idx in (("uniform", idx_uni), ("arc_targets", idx_deg)):
+        out[f"gather16_{name}"] = rate(lambda: L.sssp_ceiling_gather16(vp(idx.data_ptr()), count, vp(t16.data_ptr()),
+                                                                       vp(sink.data_ptr()), st))
+        out[f"atomic_min64_{name}"] = rate(lambda: L.sssp_ceiling_atomic_min64(vp(idx.data_ptr()), count,
+                                                                               vp(t64.data_ptr()), st))
+    out["relax_arcs_per_s"] = round(relax_arcs / (relax_ms * 1e-3) / 1e9, 2)
+    out["relax_frac_of_gather16_arc_targets"] = round(out["relax_arcs_per_s"] / out["gather16_arc_targets"], 3)
+    del idx_deg, idx_uni, t16, t64, sink
+    torch.cuda.synchronize()
+    return out
+
+
 def run_single(args, torch, sp, w):
     g = w.graph
     srcs = [int(x) for x in w.sources]
     src = srcs[0]
     G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
     torch.cuda.synchronize()
+    out = torch.empty((1, g.n), dtype=torch.int64, device="cuda")
 
     rule = "rho" if args.workload != "road5000" else "delta"
     sweep = []
+    m_reach_of = {}
     if rule == "rho":
         if args.workload == "grid256":
             choices = [4096]
@@ -170,25 +276,31 @@ def run_single(args, torch, sp, w):
         else:
             choices = []
         for rho in choices:
-            times, balg, edges_r, steps_r = [], [], [], []
-            for i in range(max(3, len(srcs))):
-                _, st = sp.solve(G, [srcs[i % len(srcs)]], rule="rho", rho=rho)
+            # One solve per source (the timed solves' sources), averaged.
+            times, balg, edges_r, steps_r, useful = [], [], [], [], []
+            for s_ in srcs:
+                _, st = sp.solve(G, [s_], rule="rho", rho=rho, out=out)
+                if s_ not in m_reach_of:
+                    m_reach_of[s_] = reachable_arcs(g, sp.to_numpy_u64(out)[0])
                 times.append(st["device_ms"])
                 balg.append(algorithmic_bytes(g.n, st, 1))
                 edges_r.append(st["edges_relaxed"])
                 steps_r.append(st["steps"])
+                useful.append(m_reach_of[s_])
             ms = float(np.mean(times))
-            sweep.append({"rho": rho, "ms": ms, "steps": int(np.mean(steps_r)),
+            sweep.append({"rho": rho, "ms": round(ms, 4), "steps": int(np.mean(steps_r)),
                           "edges_relaxed": int(np.mean(edges_r)),
-                          "gteps": float(np.mean(edges_r)) / (ms * 1e6),
+                          "gteps": round(float(np.mean(edges_r)) / (ms * 1e6), 4),
+                          "gteps_useful": round(float(np.mean(useful)) / (ms * 1e6), 4),
                           "roofline_frac": round(float(np.mean(balg)) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
-            log(f"  sweep rho=2^{rho.bit_length() - 1}: {np.median(times):.3f} ms, steps {st['steps']}, "
-                f"E_r {st['edges_relaxed']}")
+            log(f"  sweep rho=2^{rho.bit_length() - 1}: {ms:.3f} ms, steps {sweep[-1]['steps']}, "
+                f"E_r {sweep[-1]['edges_relaxed']}, frac {sweep[-1]['roofline_frac']}")
         fixed = {"rho": min(sweep, key=lambda r: r["ms"])["rho"] if sweep else (args.rho or 1 << 18)}
+        if args.rho:
+            fixed = {"rho": args.rho}
     else:
         fixed = {"delta": args.delta or int(w.params["delta"])}
 
-    out = torch.empty((1, g.n), dtype=torch.int64, device="cuda")
     for i in range(args.warmup):
         sp.solve(G, [srcs[i % len(srcs)]], rule=rule, out=out, **fixed)
 
@@ -198,8 +310,9 @@ def run_single(args, torch, sp, w):
     edges = 0
     kernel_ms = 0.0
     steps_total = 0
-    b_alg = 0
-    extracted = 0
+    b_alg = b_impl = 0
+    extracted = successes = 0
+    relax_ms = 0.0
     # Step i solves from source i mod K (the paper averages over sources;
     # all of them lie in the largest component).
     ev0.record()
@@ -209,47 +322,108 @@ def run_single(args, torch, sp, w):
         kernel_ms += st["device_ms"]
         steps_total += st["steps"]
         extracted += st["extracted"]
+        successes += st["writemin_success"]
+        relax_ms += st["phase_ms"][3]
         b_alg += algorithmic_bytes(g.n, st, 1)
+        b_impl += implementation_bytes(g.n, st, 1)
     ev1.record()
     torch.cuda.synchronize()
     total_ms = ev0.elapsed_time(ev1)
     ms_per = total_ms / args.steps
     gteps = edges / (total_ms * 1e6)
-    m_reach = reachable_arcs(g, sp.to_numpy_u64(out)[0])
+    m_reach = 0
+    for i in range(args.steps):
+        s_ = srcs[i % len(srcs)]
+        if s_ not in m_reach_of:
+            sp.solve(G, [s_], rule=rule, out=out, **fixed)
+            m_reach_of[s_] = reachable_arcs(g, sp.to_numpy_u64(out)[0])
+        m_reach += m_reach_of[s_]
 
     roofline = roofline_entry(b_alg / args.steps, kernel_ms / args.steps,
                               load_traffic(args.workload, fixed.get("rho", 0)))
+    roofline["implementation_bytes_per_launch"] = int(b_impl / args.steps)
     copy_gbs = stream_copy_gbs(torch)
     roofline["stream_copy_gbs"] = round(copy_gbs, 1)
     roofline["frac_of_stream"] = round(roofline["achieved"] / copy_gbs, 4)
+    if args.workload == "rmat24" and not args.no_ceilings:
+        try:
+            roofline["ceilings"] = measure_ceilings(torch, g, edges, relax_ms)
+        except Exception as e:
+            roofline["ceilings"] = {"error": f"{type(e).__name__}: {e}"}
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        c0 = oracle.now()
-        _, settled, scanned = oracle.dijkstra(g.offsets, g.targets, g.weights, src,
-                                              max_settled=args.cpu_settle_cap, stats=True)
-        secs = oracle.now() - c0
-        cpu = {"value": round(scanned / secs / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-               "sample": f"one binary-heap Dijkstra solve from the first source ({settled} vertices settled, "
-                         f"{scanned} arcs relaxed, {secs:.2f} s, 1 thread)"}
+    cpu = None if args.no_cpu_baseline else oracle_baseline(g, src, args.cpu_runs)
 
     config = {"workload": WORKLOADS[args.workload], "n": g.n, "m": g.m,
               "sources": srcs if len(srcs) > 1 else src, "rule": rule,
               **fixed, "steps_per_solve": int(steps_total // args.steps),
-              "edges_relaxed_per_solve": int(edges // args.steps), "useful_arcs": m_reach}
+              "edges_relaxed_per_solve": int(edges // args.steps),
+              "writemin_success_per_solve": int(successes // args.steps),
+              "useful_arcs_per_solve": int(m_reach // args.steps)}
     res = base_record(args, gteps, ms_per, config, roofline, cpu)
-    res["gteps_useful"] = round(m_reach * args.steps / (total_ms * 1e6), 4)
+    res["gteps_useful"] = round(m_reach / (total_ms * 1e6), 4)
     res["extracted_per_vertex"] = round(extracted / args.steps / g.n, 4)  # X / n
     res["relaxed_per_arc"] = round(edges / args.steps / g.m, 4)           # E_r / m
-    res["rho_sweep"] = sweep
+    if sweep:
+        best = min(sweep, key=lambda r: r["ms"])
+        res["rho_sweep"] = {"per_rho": sweep, "fastest_rho": best["rho"],
+                            "fastest_frac": best["roofline_frac"],
+                            "what": "one solve per source per rho, averaged; the timed solves use the fastest rho"}
     G.close()
+    torch.cuda.synchronize()
     return res
 
 
-def run_batched(args, torch, sp, w):
+def run_road_sweep(args, torch, sp):
+    """Delta*-stepping over Delta = 2^10 .. 2^16 and Bellman-Ford on the road
+    workload, one solve each from its seeded source: time, steps, time per
+    step (the paper's Delta and BF rows; Sec. 6 on road graphs)."""
+    import graphgen
+    w = graphgen.workload("road5000", sources=1)
+    g = w.graph
+    src = int(w.sources[0])
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+    out = torch.empty((1, g.n), dtype=torch.int64, device="cuda")
+    sp.solve(G, [src], rule="delta", delta=1 << 15, out=out)  # warm-up
+    m_reach = reachable_arcs(g, sp.to_numpy_u64(out)[0])
+    rows = []
+    for lg in list(range(10, 17)) + ["bf"]:
+        kw = {"rule": "bf"} if lg == "bf" else {"rule": "delta", "delta": 1 << lg}
+        _, st = sp.solve(G, [src], out=out, **kw)
+        ms = st["device_ms"]
+        rows.append({"delta": None if lg == "bf" else 1 << lg, "rule": kw["rule"], "ms": round(ms, 3),
+                     "steps": int(st["steps"]), "us_per_step": round(ms * 1e3 / max(1, st["steps"]), 2),
+                     "edges_relaxed": int(st["edges_relaxed"]), "gteps": round(st["edges_relaxed"] / (ms * 1e6), 4),
+                     "gteps_useful": round(m_reach / (ms * 1e6), 4),
+                     "local_vertices": int(st["local_vertices"])})
+        log(f"  road5000 {kw}: {ms:.2f} ms, {st['steps']} steps")
+    G.close()
+    torch.cuda.synchronize()
+    best = min((r for r in rows if r["rule"] == "delta"), key=lambda r: r["ms"])
+    return {"workload": WORKLOADS["road5000"], "n": g.n, "m": g.m, "source": src, "useful_arcs": m_reach,
+            "per_rule": rows, "fastest_delta": best["delta"]}
+
+
+def run_knn_compare(args, torch, sp):
+    """The batched workload at fixed settings (from an earlier tuning run):
+    64 queries in one launch against the same 64 queries one launch each."""
+    import graphgen
+    w = graphgen.workload("knn10000", sources=64)
+    la = argparse.Namespace(**vars(args))
+    la.tune_budget, la.no_cpu_baseline, la.steps, la.warmup = 0.0, True, 3, 1
+    la.workload = "knn10000"
+    r = run_batched(la, torch, sp, w, cfg_fixed=({"rule": "delta", "delta": 1898},
+                                                 {"rule": "delta", "delta": 3796}))
+    keep = ("queries_per_s", "batched_speedup", "gteps_useful", "plain", "ms_per_step", "value")
+    res = {k: r[k] for k in keep}
+    res["config"] = {k: r["config"][k] for k in ("n", "m", "queries", "rule", "delta", "teams")}
+    res["workload"] = WORKLOADS["knn10000"]
+    return res
+
+
+def run_batched(args, torch, sp, w, cfg_fixed=None):
     """All sources in one launch (teams chosen by the library) against the
-    same sources one launch each (one whole-grid team)."""
+    same sources one launch each (one whole-grid team). cfg_fixed: (batched,
+    plain) settings to use instead of the defaults or a tuning run."""
     g = w.graph
     srcs = [int(x) for x in w.sources]
     nq = len(srcs)
@@ -265,7 +439,9 @@ def run_batched(args, torch, sp, w):
         return sp.solve(G, sources, rule=cfg["rule"], tuning=tun or None, out=dst, **kw)
 
     default = {"rule": "rho", "rho": args.rho or int(w.params["rho"])}
-    if args.tune_budget > 0:
+    if cfg_fixed is not None:
+        cfg_b, cfg_p = cfg_fixed
+    elif args.tune_budget > 0:
         # Batched: the parameter search times the whole batch. Plain: it times
         # the first 8 queries one launch each, with one whole-grid team.
         t0 = time.time()
@@ -293,7 +469,7 @@ def run_batched(args, torch, sp, w):
         _, st = call(cfg_b, srcs, out)
         edges += st["edges_relaxed"]
         kernel_ms += st["device_ms"]
-        b_alg += algorithmic_bytes(g.n, st, nq, relabelled=False)
+        b_alg += algorithmic_bytes(g.n, st, nq)
     ev1.record()
     torch.cuda.synchronize()
     total_ms = ev0.elapsed_time(ev1)
@@ -326,7 +502,7 @@ def run_batched(args, torch, sp, w):
         secs = oracle.now() - c0
         cpu = {"value": round(scanned_total / secs / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
                "sample": f"the same {nq} queries, one binary-heap Dijkstra each ({scanned_total} arcs relaxed, "
-                         f"{secs:.2f} s, 1 thread, {nq / secs:.2f} queries/s)"}
+                         f"{secs:.2f} s, 1 thread, {nq / secs:.2f} queries/s)", **host_cpu()}
 
     strip = lambda c: {k: v for k, v in c.items() if k in ("rule", "rho", "delta", "tuning")}
     config = {"workload": WORKLOADS[args.workload], "n": g.n, "m": g.m, "queries": nq, **strip(cfg_b),
@@ -386,10 +562,15 @@ def run_serve(args, torch, sp):
     # and on 8 single queries per graph (plain).
     cfg_s, cfg_p = [], []
     if args.tune_budget <= 0:
-        # Settings a full tuning run of this workload chose (served: batches of
-        # 32 queries; plain: one query at a time on the whole grid).
-        cfg_s = [{"rule": "rho", "rho": 1 << 14, "tuning": {}}, {"rule": "delta", "delta": 8448, "tuning": {}}]
+        # Settings a full tuning run of this workload chose for one query at a
+        # time on the whole grid. The servers' rho and Delta are per team (a
+        # group of k teams uses k times them): the whole-grid values divided
+        # by the server's team count, so a request that arrives at a quiet
+        # server, solved by all its teams, runs with the plain loop's values.
         cfg_p = [{"rule": "rho", "rho": 1 << 17, "tuning": {}}, {"rule": "delta", "delta": 67584, "tuning": {}}]
+        nteams = [int(x) for x in args.serve_teams.split(",")]
+        cfg_s = [{"rule": "rho", "rho": args.serve_rho or max(1, (1 << 17) // nteams[0]), "tuning": {}},
+                 {"rule": "delta", "delta": args.serve_delta or max(1, 67584 // nteams[1]), "tuning": {}}]
     for k in ((0, 1) if args.tune_budget > 0 else ()):
         ks = [int(x) for x in src[which == k][:32]]
         tb = at.Tuner(budget_s=args.tune_budget / 2)
@@ -408,12 +589,12 @@ def run_serve(args, torch, sp):
 
     out1 = [torch.empty((1, g.n), dtype=torch.int64, device="cuda") for g in graphs]
 
-    def plain_loop(arrive):
+    def plain_loop(arrive, count):
         """One query at a time, whole grid each; returns (latencies, hashes, makespan)."""
-        lat = np.zeros(nq)
-        hashes = [0] * nq
+        lat = np.zeros(count)
+        hashes = [0] * count
         start = time.perf_counter()
-        for i in range(nq):
+        for i in range(count):
             k = int(which[i])
             now = time.perf_counter() - start
             if now < arrive[i]:
@@ -422,58 +603,63 @@ def run_serve(args, torch, sp):
             sp.solve(G[k], [int(src[i])], tuning=tun, out=out1[k], stream=side, **params(cfg_p[k]))
             hashes[i] = sp.row_hash(out1[k][0], stream=side)
             lat[i] = time.perf_counter() - start - arrive[i]
-            if (i + 1) % 50 == 0:
-                log(f"  plain: {i + 1}/{nq} queries, {time.perf_counter() - start:.1f}s")
+            if (i + 1) % 200 == 0:
+                log(f"  plain: {i + 1}/{count} queries, {time.perf_counter() - start:.1f}s")
         return lat, hashes, time.perf_counter() - start
 
-    nrows = args.rows
     serve_teams = [int(x) for x in args.serve_teams.split(",")]
     serve_bpc = [int(x) for x in args.serve_bpc.split(",")]
-    rows = [torch.empty((nrows, g.n), dtype=torch.int64, device="cuda") for g in graphs]
+    # The admission budget, split between the two servers in proportion to
+    # their grids.
+    budget = int(args.serve_budget_gib * (1 << 30))
+    budgets = [budget * serve_bpc[0] // sum(serve_bpc), budget * serve_bpc[1] // sum(serve_bpc)]
 
-    def served_loop(arrive):
-        """Both graphs' servers running; queries admitted in arrival order as
-        rows free up; returns (latencies, hashes, makespan, stats)."""
-        servers = [sp.Server(G[k], rows[k], tuning={**(cfg_s[k].get("tuning") or {}), "blocks_per_cu": serve_bpc[k],
-                                                    "teams": serve_teams[k]}, hash_rows=True,
-                             ring_capacity=2 * nrows, stream=side, **params(cfg_s[k])) for k in (0, 1)]
-        free = [list(range(nrows)), list(range(nrows))]
+    def served_loop(arrive, count):
+        """Both graphs' budget servers running; queries enqueued at arrival and
+        admitted as rows of the budget free up (a finished query's row is
+        released as soon as it is polled); returns (latencies, hashes,
+        makespan, stats, most rows in use)."""
+        servers = [sp.BudgetServer(G[k], budgets[k], tuning={**(cfg_s[k].get("tuning") or {}),
+                                                             "blocks_per_cu": serve_bpc[k], "teams": serve_teams[k]},
+                                   hash_rows=True, stream=side, **params(cfg_s[k])) for k in (0, 1)]
         ticket = [{}, {}]
-        lat = np.zeros(nq)
-        hashes = [0] * nq
-        waiting = [[], []]  # arrived, not yet admitted (per graph, FIFO)
+        lat = np.zeros(count)
+        hashes = [0] * count
         nxt = done = 0
+        peak_rows = [0, 0]
         start = time.perf_counter()
         last_log = last_done = start
         try:
-            while done < nq:
+            while done < count:
                 now_abs = time.perf_counter()
                 if now_abs - last_log > 5.0:
                     last_log = now_abs
-                    log(f"  served: {done}/{nq} queries, {now_abs - start:.1f}s")
+                    log(f"  served: {done}/{count} queries, {now_abs - start:.1f}s")
                 if now_abs - last_done > 60.0:
                     # Both servers must be resident at once; a tool that runs
                     # kernels one at a time (a counter-collecting profiler)
                     # leaves the second waiting for the first to go idle.
-                    raise RuntimeError(f"serving stalled at {done}/{nq} queries")
+                    raise RuntimeError(f"serving stalled at {done}/{count} queries")
                 now = now_abs - start
-                while nxt < nq and arrive[nxt] <= now:
-                    waiting[int(which[nxt])].append(nxt)
+                while nxt < count and arrive[nxt] <= now:
+                    k = int(which[nxt])
+                    ticket[k][servers[k].enqueue(int(src[nxt]))] = nxt
                     nxt += 1
                 for k in (0, 1):
                     S = servers[k]
-                    while waiting[k] and free[k]:
-                        i = waiting[k].pop(0)
-                        r = free[k].pop()
-                        ticket[k][S.submit(int(src[i]), r)] = (i, r)
-                    for t, h in S.poll():
-                        i, r = ticket[k].pop(t)
+                    fin = S.poll()
+                    if fin:
+                        c = S.counts()
+                        peak_rows[k] = max(peak_rows[k], c["admitted"] + c["held"])
+                    for t, h in fin:
+                        i = ticket[k].pop(t)
                         lat[i] = time.perf_counter() - start - arrive[i]
                         hashes[i] = h
-                        free[k].append(r)
+                        S.release(t)
                         done += 1
                         last_done = time.perf_counter()
             makespan = time.perf_counter() - start
+            rows_avail = [S.counts()["rows"] for S in servers]
             stats = [S.stop() for S in servers]
         finally:
             for S in servers:
@@ -483,23 +669,26 @@ def run_serve(args, torch, sp):
                     pass
             for S in servers:
                 S.close()
-        return lat, hashes, makespan, stats
+        return lat, hashes, makespan, stats, {"rows": rows_avail, "peak_rows_in_use": peak_rows}
 
-    # Closed loop: everything queued at t = 0.
-    zero = np.zeros(nq)
-    lat_p0, hash_p, span_p0 = plain_loop(zero)
-    rate_plain = nq / span_p0
+    # Closed loop (the trace's first queries all queued at t = 0): saturation
+    # rates of both systems.
+    nc = min(nq, args.closed_queries) if args.closed_queries > 0 else nq
+    zero = np.zeros(nc)
+    lat_p0, hash_p, span_p0 = plain_loop(zero, nc)
+    rate_plain = nc / span_p0
     log(f"plain closed loop: {span_p0:.2f}s, {rate_plain:.1f} q/s")
-    lat_s0, hash_s0, span_s0, _ = served_loop(zero)
-    log(f"served closed loop: {span_s0:.2f}s, {nq / span_s0:.1f} q/s")
-    # Open loop at 0.8 x the plain saturation rate.
+    lat_s0, hash_s0, span_s0, _, _ = served_loop(zero, nc)
+    log(f"served closed loop: {span_s0:.2f}s, {nc / span_s0:.1f} q/s")
+    # Open loop over the whole trace at 0.8 x the plain saturation rate.
     lam = 0.8 * rate_plain
     arrive = np.cumsum(gaps) / lam
-    lat_p1, hash_p1, span_p1 = plain_loop(arrive)
-    lat_s1, hash_s1, span_s1, sstats = served_loop(arrive)
+    lat_p1, hash_p1, span_p1 = plain_loop(arrive, nq)
+    lat_s1, hash_s1, span_s1, sstats, rowinfo = served_loop(arrive, nq)
     log(f"open loop lambda={lam:.1f}/s: plain p50 {np.median(lat_p1) * 1e3:.1f} ms, served p50 "
         f"{np.median(lat_s1) * 1e3:.1f} ms")
-    same = all(hash_p[i] == hash_s0[i] == hash_p1[i] == hash_s1[i] for i in range(nq))
+    same = all(hash_p1[i] == hash_s1[i] for i in range(nq)) and \
+        all(hash_p[i] == hash_s0[i] == hash_p1[i] for i in range(nc))
     # Oracle sample.
     checked = 0
     if not args.no_cpu_baseline:
@@ -529,13 +718,16 @@ def run_serve(args, torch, sp):
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS["serve"], "queries": nq, "rows_per_graph": nrows,
+        "config": {"workload": WORKLOADS["serve"], "queries": nq, "closed_loop_queries": nc,
+                   "admission_budget_bytes": budgets, "result_rows": rowinfo["rows"],
+                   "peak_rows_in_use": rowinfo["peak_rows_in_use"],
                    "server_teams": serve_teams, "server_blocks_per_cu": serve_bpc,
                    "served": [params(c) | {"tuning": c.get("tuning")} for c in cfg_s],
                    "plain": [params(c) | {"tuning": c.get("tuning")} for c in cfg_p]},
-        "closed_loop": {"plain_qps": round(rate_plain, 2), "served_qps": round(nq / span_s0, 2),
+        "closed_loop": {"queries": nc, "plain_qps": round(rate_plain, 2), "served_qps": round(nc / span_s0, 2),
                         "speedup": round(span_p0 / span_s0, 3)},
         "open_loop": {"lambda_qps": round(lam, 2),
+                      "plain_qps": round(nq / span_p1, 2), "served_qps": round(nq / span_s1, 2),
                       "plain_ms": {"p50": pct(lat_p1, 50), "p99": pct(lat_p1, 99)},
                       "served_ms": {"p50": pct(lat_s1, 50), "p99": pct(lat_s1, 99)},
                       "by_graph_p50_ms": {"rmat": [pct(lat_p1[which == 0], 50), pct(lat_s1[which == 0], 50)],
@@ -562,26 +754,41 @@ def main():
     ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
     ap.add_argument("--rho", type=int, default=0, help="rho for the timed solves (0 = the workload's default)")
     ap.add_argument("--delta", type=int, default=0, help="Delta for the road workload (0 = its default, 2^15)")
-    ap.add_argument("--sweep", default="", metavar="LOG2_LIST",
-                    help="e.g. 16,17,18,19,20,21,22: time 3 solves per rho first and use the fastest")
+    ap.add_argument("--sweep", default="16,17,18,19,20,21,22", metavar="LOG2_LIST",
+                    help="rho values (log2) timed first, one solve per source each; the timed solves use the "
+                         "fastest ('' = no sweep)")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="rmat24: skip the gather / atomic-minimum ceiling microbenchmarks")
+    ap.add_argument("--cpu-runs", type=int, default=3, help="timed runs of the CPU oracle (the median is reported)")
+    ap.add_argument("--extras", default="road,knn,latency",
+                    help="rmat24: further workloads whose figures join the line (road: Delta / BF sweep on "
+                         "road5000; knn: 64 batched queries against 64 single launches; latency: a short "
+                         "serving run); '' = none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sources", type=int, default=10,
                     help="rmat24: seeded sources in the largest component; timed solve i uses source i mod K")
     ap.add_argument("--queries", type=int, default=600, help="serving: queries in the trace")
     ap.add_argument("--latency-queries", type=int, default=200,
                     help="rmat24: queries of the short serving run whose p50/p99 join the line (0 = skip)")
-    ap.add_argument("--rows", type=int, default=64, help="serving: result rows (admission slots) per graph")
+    ap.add_argument("--closed-queries", type=int, default=2000,
+                    help="serving: queries of the closed-loop (saturation) runs, a prefix of the trace (0 = all)")
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0,
+                    help="serving: device-memory admission budget (GiB), split between the servers in "
+                         "proportion to their grids")
     ap.add_argument("--serve-bpc", default="3,1",
                     help="serving: workgroups per CU of the R-MAT and grid servers (sum at most 4)")
-    ap.add_argument("--serve-teams", default="8,8",
-                    help="serving: teams of the R-MAT and grid servers (with --serve-bpc 3,1 on 256 CUs: 8 "
-                         "R-MAT teams of 96 workgroups, 8 grid teams of 32)")
+    ap.add_argument("--serve-teams", default="32,16",
+                    help="serving: teams of the R-MAT and grid servers (with --serve-bpc 3,1 on 256 CUs: 32 "
+                         "R-MAT teams of 24 workgroups, 16 grid teams of 16); a request takes a group of "
+                         "idle teams, all of them when it is alone")
+    ap.add_argument("--serve-rho", type=int, default=0,
+                    help="serving: the R-MAT server's rho per team (0 = 2^17 / its teams)")
+    ap.add_argument("--serve-delta", type=int, default=0,
+                    help="serving: the grid server's Delta per team (0 = 67584 / its teams)")
     ap.add_argument("--oracle-sample", type=int, default=4, help="serving: queries per graph checked by the oracle")
     ap.add_argument("--tune-budget", type=float, default=20.0,
                     help="seconds of parameter search per mode for the batched and serving workloads "
                          "(0 = the workload defaults, or for serving the settings of an earlier full search)")
-    ap.add_argument("--cpu-settle-cap", type=int, default=0,
-                    help="stop the CPU oracle after this many settled vertices (0 = full solve)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB (5 times) and exit; "
                          "used to scale the FETCH_SIZE / WRITE_SIZE counters")
@@ -624,12 +831,26 @@ def main():
         res = run_batched(args, torch, sp, w)
     else:
         res = run_single(args, torch, sp, w)
-        if args.workload == "rmat24" and args.latency_queries > 0:
+        extras = [x for x in args.extras.split(",") if x] if args.workload == "rmat24" else []
+        del w
+        # Further workloads of the metric, each in its own key; a failure in
+        # one is recorded there and leaves the throughput line standing.
+        if "road" in extras:
+            try:
+                res["road_delta_sweep"] = run_road_sweep(args, torch, sp)
+            except Exception as e:
+                res["road_delta_sweep"] = {"error": f"{type(e).__name__}: {e}"}
+        if "knn" in extras:
+            try:
+                res["knn_batched"] = run_knn_compare(args, torch, sp)
+            except Exception as e:
+                res["knn_batched"] = {"error": f"{type(e).__name__}: {e}"}
+        if "latency" in extras and args.latency_queries > 0:
             # The metric's latency half: a short serving run (both graphs of the
             # serving workload resident) against the one-at-a-time loop.
-            del w
             la = argparse.Namespace(**vars(args))
             la.queries, la.tune_budget, la.oracle_sample = args.latency_queries, 0.0, 1
+            la.closed_queries = args.latency_queries
             try:
                 srv = run_serve(la, torch, sp)
                 res["latency"] = {k: srv[k] for k in ("closed_loop", "open_loop", "same_alone_and_in_the_mix",
@@ -638,6 +859,7 @@ def main():
                 res["latency"]["queries"] = la.queries
             except Exception as e:  # the throughput line above stands on its own
                 res["latency"] = {"error": f"{type(e).__name__}: {e}"}
+    torch.cuda.synchronize()
     print(json.dumps(res), flush=True)
 
 

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define SSSP_ABI_VERSION 2
+#define SSSP_ABI_VERSION 3
 
 typedef enum {
   SSSP_OK = 0,
@@ -65,7 +65,10 @@ typedef enum {
    * queue, log q = 1 + log2(q + 1), taking the ceil(rho * s / q)-th smallest
    * (App. B, c = 10). If q <= rho the whole queue is extracted. The first two
    * steps whose queue holds more than floor(rho / 10) vertices use
-   * floor(rho / 10) instead of rho (Sec. 6). */
+   * floor(rho / 10) instead of rho (Sec. 6). s is capped at
+   * tuning.sample_cap and, in steps that scan the bitmap, by the probes
+   * tuning.probe_cap allows (see sssp_tuning); the rank ceil(rho s / q) uses
+   * the number of samples actually drawn. */
   SSSP_RULE_RHO = 0,
   /* Delta*-stepping (Table 2, Thm. 5.5): theta = i * Delta, i = 1, 2, ...
    * advancing every step, skipping ahead to ceil(min key / Delta) when the
@@ -99,6 +102,14 @@ typedef enum { SSSP_OFFSETS_I32 = 0, SSSP_OFFSETS_I64 = 1 } sssp_offset_width;
 #define SSSP_KEEP_ORDER 0x8u   /* keep the caller's vertex numbering internally (by default the
                                   library renumbers vertices by decreasing out-degree for cache
                                   locality; results are always in the caller's ids) */
+#define SSSP_BORROW_DEVICE 0x20u /* with SSSP_INPUT_DEVICE: use the caller's targets and weights
+                                  arrays in place instead of copying them into the library's packed
+                                  arcs (saves 8 bytes per arc; each arc is then read as two 4-byte
+                                  loads). Implies SSSP_KEEP_ORDER. Offsets are still copied (8 (n+1)
+                                  bytes). The caller keeps both arrays allocated, at the same
+                                  addresses, until sssp_graph_destroy; weights it changes in place
+                                  between solves are the weights of the next solve (targets must
+                                  stay valid: they are checked only at creation) */
 
 /* Tuning knobs. Zero in any field selects the library default. None of them
  * changes the distances; they change speed, steps and work only. */
@@ -110,8 +121,11 @@ typedef struct {
   uint32_t chunk_edges;   /* edges per hub chunk */
   uint32_t list_divisor;  /* keep an explicit frontier list while |Q| <= n / list_divisor;
                              0xFFFFFFFF disables the list (bitmap scans only) */
-  uint32_t sample_cap;    /* maximum rho-stepping sample size */
-  uint32_t probe_cap;     /* maximum bitmap probes per sampled step */
+  uint32_t sample_cap;    /* maximum rho-stepping sample size (default 2^16: App. B's s is
+                             drawn whole unless it exceeds this) */
+  uint32_t probe_cap;     /* maximum bitmap probes per sampled step (default 2^16; a bitmap
+                             step probes about 1.25 s n / q vertex ids, keeping those in Q,
+                             so at most about probe_cap q / n samples are drawn there) */
   uint32_t no_filter;     /* 1 = skip the read-before-atomic filter in Relax */
   uint32_t teams;         /* independent solves in flight: the persistent grid is split into
                              this many teams of workgroups, each solving one source at a time
@@ -149,7 +163,12 @@ typedef struct {
                              is at most theta. Same extracted sets, so the same distances.
                              In this mode hub_degree is capped at 64 (a workgroup extracts
                              4096 consecutive vertices, so larger rows are shared instead) */
-  uint32_t reserved2;
+  uint32_t repeat_skip;   /* skip pushing a vertex's arcs (or a hub chunk's) again when its key has
+                             not changed since they were last pushed: every such WriteMin would
+                             fail. Costs 8 bytes per vertex and per hub chunk for each team.
+                             0 = library default (on for launches of one team on graphs whose
+                             average out-degree is at least super_sparse_degree), 1 = on,
+                             0xFFFFFFFF = off */
 } sssp_tuning;
 
 /* One record per step, written when params.trace is set. */
@@ -217,6 +236,9 @@ typedef struct {
   uint64_t queue_list;       /* sum of |Q| over steps whose Extract read the explicit list */
   uint64_t list_appends;     /* entries written to explicit lists (kept and new members) */
   uint64_t local_vertices;   /* vertices relaxed by local expansion (not counted in extracted) */
+  uint64_t repeat_skipped;   /* arcs not pushed again because their tail's key had not changed since
+                                they were last pushed (every such WriteMin would fail; not counted
+                                in edges_relaxed) */
 } sssp_stats;
 
 typedef struct sssp_graph sssp_graph; /* opaque */
@@ -237,10 +259,12 @@ void sssp_default_params(sssp_params* p);
  *   weights  m uint32 entries (zero allowed). Parallel arcs and self-loops
  *            are allowed.
  *   flags    exactly one of SSSP_INPUT_HOST / SSSP_INPUT_DEVICE, optionally
- *            SSSP_TRUST_INPUT.
+ *            SSSP_TRUST_INPUT, SSSP_KEEP_ORDER, SSSP_UNDIRECTED and (with
+ *            SSSP_INPUT_DEVICE) SSSP_BORROW_DEVICE.
  *   stream   stream for the upload (the call returns after it completes).
- * The library copies the arrays into its own device layout; the caller keeps
- * ownership of its arrays and may free them on return. Errors:
+ * The library copies the arrays into its own device layout (unless
+ * SSSP_BORROW_DEVICE); the caller keeps ownership of its arrays and may free
+ * them on return (with SSSP_BORROW_DEVICE: only its offsets array). Errors:
  * INVALID_ARGUMENT, INVALID_GRAPH (validation failed; detail names the first
  * offending index), OUT_OF_MEMORY, NO_DEVICE, DEVICE. On error *out is NULL.
  */
@@ -375,7 +399,9 @@ sssp_status sssp_row_hash(const uint64_t* dist, int64_t n, void* stream, uint64_
  * on the legacy NULL stream waits for it, so keep such work on non-blocking
  * streams (hipStreamNonBlocking).
  *   params   rule and parameters as for sssp_solve (trace, extract_counts and
- *            max_steps must be unset).
+ *            max_steps must be unset). rho and Delta are per team: a request
+ *            solved by a group of k teams uses k * rho and k * Delta (its
+ *            work per step grows with its workgroups).
  *   dist_rows device pointer to rows * n uint64 entries; a request names the
  *            row its distances go to, and holds it until it is polled done
  *            (rows bound the requests in flight). The caller owns the memory.

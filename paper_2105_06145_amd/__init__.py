@@ -108,13 +108,16 @@ class Graph:
 
     @classmethod
     def from_csr(cls, offsets, targets, weights, validate: bool = True, reorder: bool = True,
-                 undirected: bool = False, stream=None) -> "Graph":
+                 undirected: bool = False, borrow: bool = False, stream=None) -> "Graph":
         """offsets (n+1, int32 or int64), targets (m, int32), weights (m,
         uint32): numpy arrays (host) or torch CUDA tensors (device). The
         library copies them into its own layout (renumbered by decreasing
         degree unless reorder=False; results always use the caller's ids).
         undirected=True asserts symmetric arcs (checked unless validate=False)
-        and allows bidirectional relaxation (tuning pull=1)."""
+        and allows bidirectional relaxation (tuning pull=1). borrow=True (torch
+        CUDA inputs only) uses the targets and weights tensors in place
+        (SSSP_BORROW_DEVICE; caller order kept): the Graph holds references to
+        them until it is closed."""
         torch = _torch()
         flags = (0 if validate else N.SSSP_TRUST_INPUT) | (0 if reorder else N.SSSP_KEEP_ORDER) | \
             (N.SSSP_UNDIRECTED if undirected else 0)
@@ -130,9 +133,11 @@ class Graph:
             n = offsets.numel() - 1
             m = targets.numel()
             ptrs = [ctypes.c_void_p(t.data_ptr()) for t in (offsets, targets, weights)]
-            flags |= N.SSSP_INPUT_DEVICE
+            flags |= N.SSSP_INPUT_DEVICE | (N.SSSP_BORROW_DEVICE if borrow else 0)
             keep = (offsets, targets, weights)
         else:
+            if borrow:
+                raise ValueError("borrow=True needs torch CUDA tensors")
             off = np.ascontiguousarray(offsets)
             if off.dtype not in (np.int32, np.int64):
                 off = off.astype(np.int64)
@@ -146,10 +151,11 @@ class Graph:
             flags |= N.SSSP_INPUT_HOST
             keep = (off, tgt, w)
         rc, h = sssp_graph_create(n, m, ow, ptrs[0], ptrs[1], ptrs[2], flags, _stream_ptr(stream))
-        del keep
         if rc != N.SSSP_OK:
             raise SSSPError(rc, "sssp_graph_create")
-        return cls(h, n, m, summary)
+        G = cls(h, n, m, summary)
+        G._borrowed = keep[1:] if borrow else None
+        return G
 
     def device_bytes(self) -> int:
         rc, _, _, b = sssp_graph_info(self._h)
@@ -161,6 +167,7 @@ class Graph:
         if getattr(self, "_h", None) is not None:
             sssp_graph_destroy(self._h)
             self._h = None
+        self._borrowed = None
 
     def __del__(self):
         try:

@@ -16,6 +16,9 @@ _REPO = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libsssp.so")
 SOURCES = [os.path.join(_HERE, "csrc", "stepping.hip"), os.path.join(_HERE, "csrc", "graph.hip")]
 HEADER = os.path.join(_REPO, "include", "sssp.h")
+CEIL_LIB_PATH = os.path.join(_HERE, "libsssp_ceilings.so")
+CEIL_SOURCES = [os.path.join(_HERE, "csrc", "ceilings.hip")]
+CEIL_HEADER = os.path.join(_REPO, "include", "sssp_ceilings.h")
 
 HIPCC_FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -49,6 +52,7 @@ SSSP_INPUT_DEVICE = 0x2
 SSSP_TRUST_INPUT = 0x4
 SSSP_KEEP_ORDER = 0x8
 SSSP_UNDIRECTED = 0x10
+SSSP_BORROW_DEVICE = 0x20
 SSSP_SOLVE_SNAPSHOT_KEYS = 0x1
 SSSP_SERVE_HASH = 0x1
 
@@ -60,7 +64,7 @@ class sssp_tuning(ctypes.Structure):
                 ("no_filter", ctypes.c_uint32), ("teams", ctypes.c_uint32),
                 ("local_budget", ctypes.c_uint32), ("super_sparse_degree", ctypes.c_uint32),
                 ("pull", ctypes.c_uint32), ("group_max", ctypes.c_uint32), ("queue", ctypes.c_uint32),
-                ("reserved2", ctypes.c_uint32)]
+                ("repeat_skip", ctypes.c_uint32)]
 
 
 class sssp_step_record(ctypes.Structure):
@@ -83,7 +87,8 @@ class sssp_stats(ctypes.Structure):
                 ("sampled_steps", ctypes.c_uint64), ("device_ms", ctypes.c_double),
                 ("phase_ms", ctypes.c_double * 4), ("relax_wg_ms", ctypes.c_double * 2),
                 ("teams", ctypes.c_uint64), ("queue_dense", ctypes.c_uint64), ("queue_list", ctypes.c_uint64),
-                ("list_appends", ctypes.c_uint64), ("local_vertices", ctypes.c_uint64)]
+                ("list_appends", ctypes.c_uint64), ("local_vertices", ctypes.c_uint64),
+                ("repeat_skipped", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -102,12 +107,33 @@ class sssp_server_load(ctypes.Structure):
 
 
 def build(force: bool = True) -> str:
-    """Compile libsssp.so for gfx950 with hipcc (in-tree)."""
-    if force or not os.path.exists(LIB_PATH):
-        tmp = LIB_PATH + ".tmp"
-        subprocess.check_call(["hipcc", *HIPCC_FLAGS, *SOURCES, "-o", tmp])
-        os.replace(tmp, LIB_PATH)
+    """Compile libsssp.so and libsssp_ceilings.so for gfx950 with hipcc (in-tree)."""
+    for path, srcs in ((LIB_PATH, SOURCES), (CEIL_LIB_PATH, CEIL_SOURCES)):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.check_call(["hipcc", *HIPCC_FLAGS, *srcs, "-o", tmp])
+            os.replace(tmp, path)
     return LIB_PATH
+
+
+_ceil = None
+
+
+def ceilings_lib():
+    """Load libsssp_ceilings.so (the memory-ceiling microbenchmarks; raises
+    if it has not been built)."""
+    global _ceil
+    if _ceil is None:
+        if not os.path.exists(CEIL_LIB_PATH):
+            raise RuntimeError(f"{CEIL_LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(CEIL_LIB_PATH)
+        vp = ctypes.c_void_p
+        L.sssp_ceiling_gather16.argtypes = [vp, ctypes.c_uint64, vp, vp, vp]
+        L.sssp_ceiling_gather16.restype = ctypes.c_int
+        L.sssp_ceiling_atomic_min64.argtypes = [vp, ctypes.c_uint64, vp, vp]
+        L.sssp_ceiling_atomic_min64.restype = ctypes.c_int
+        _ceil = L
+    return _ceil
 
 
 _lib = None

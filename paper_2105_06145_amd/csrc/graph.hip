@@ -270,8 +270,11 @@ sssp_status sssp_graph_create(int64_t n, int64_t m, sssp_offset_width ow, const 
     return fail(SSSP_ERR_INVALID_ARGUMENT, "int32 offsets need m < 2^31");
   const bool host = (flags & SSSP_INPUT_HOST) != 0, device = (flags & SSSP_INPUT_DEVICE) != 0;
   if (host == device) return fail(SSSP_ERR_INVALID_ARGUMENT, "exactly one of SSSP_INPUT_HOST/DEVICE");
-  if (flags & ~(SSSP_INPUT_HOST | SSSP_INPUT_DEVICE | SSSP_TRUST_INPUT | SSSP_KEEP_ORDER | SSSP_UNDIRECTED))
+  if (flags & ~(SSSP_INPUT_HOST | SSSP_INPUT_DEVICE | SSSP_TRUST_INPUT | SSSP_KEEP_ORDER | SSSP_UNDIRECTED |
+                SSSP_BORROW_DEVICE))
     return fail(SSSP_ERR_INVALID_ARGUMENT, "unknown flag bits");
+  const bool borrow = (flags & SSSP_BORROW_DEVICE) != 0;
+  if (borrow && !device) return fail(SSSP_ERR_INVALID_ARGUMENT, "SSSP_BORROW_DEVICE needs SSSP_INPUT_DEVICE");
   if (!offsets || (m > 0 && (!targets || !weights))) return fail(SSSP_ERR_INVALID_ARGUMENT, "NULL array");
   const bool trust = (flags & SSSP_TRUST_INPUT) != 0;
 
@@ -316,7 +319,7 @@ sssp_status sssp_graph_create(int64_t n, int64_t m, sssp_offset_width ow, const 
   hipError_t e = hipSuccess;
   do {
     if ((e = g->off.alloc((size_t)(n + 1) * 8, st)) != hipSuccess) break;
-    if ((e = g->edges.alloc((size_t)m * 8, st)) != hipSuccess) break;
+    if (!borrow && (e = g->edges.alloc((size_t)m * 8, st)) != hipSuccess) break;
     if (ow == SSSP_OFFSETS_I64) {
       if ((e = hipMemcpyAsync(g->off.p, offsets, (size_t)(n + 1) * 8, kind, st)) != hipSuccess) break;
     } else {
@@ -352,14 +355,24 @@ sssp_status sssp_graph_create(int64_t n, int64_t m, sssp_offset_width ow, const 
         break;
       }
     }
-    if (m > 0) {
-      pack_edges_kernel<<<2048, 256, 0, st>>>(tsrc, wsrc, (ull*)g->edges.p, (ull)m);
+    // Borrowed arrays stay as they are; the symmetry check below reads a
+    // packed copy made for it alone.
+    DevBuf& packed = borrow ? t32 : g->edges;
+    const bool check_sym = (flags & SSSP_UNDIRECTED) && !trust && m > 0;
+    if (borrow) {
+      g->borrowed = true;
+      g->btgt = targets;
+      g->bwt = weights;
+      if (check_sym && (e = packed.alloc((size_t)m * 8, st)) != hipSuccess) break;
+    }
+    if (m > 0 && (!borrow || check_sym)) {
+      pack_edges_kernel<<<2048, 256, 0, st>>>(tsrc, wsrc, (ull*)packed.p, (ull)m);
       if ((e = hipGetLastError()) != hipSuccess) break;
     }
-    if ((flags & SSSP_UNDIRECTED) && !trust && m > 0) {
+    if (check_sym) {
       if ((e = flag.alloc(16, st)) != hipSuccess) break;
       if ((e = hipMemsetAsync(flag.p, 0, 16, st)) != hipSuccess) break;
-      symmetry_hash_kernel<<<1024, 256, 0, st>>>((const int64_t*)g->off.p, (const ull*)g->edges.p, (ull)n,
+      symmetry_hash_kernel<<<1024, 256, 0, st>>>((const int64_t*)g->off.p, (const ull*)packed.p, (ull)n,
                                                  (ull*)flag.p);
       ull sums[2] = {0, 1};
       if ((e = hipGetLastError()) == hipSuccess &&
@@ -379,7 +392,7 @@ sssp_status sssp_graph_create(int64_t n, int64_t m, sssp_offset_width ow, const 
   w32.release(st);
   o32.release(st);
   flag.release(st);
-  if (e == hipSuccess && rs == SSSP_OK && !(flags & SSSP_KEEP_ORDER)) rs = relabel_by_degree(g, st);
+  if (e == hipSuccess && rs == SSSP_OK && !(flags & SSSP_KEEP_ORDER) && !borrow) rs = relabel_by_degree(g, st);
   if (e != hipSuccess) {
     sssp_graph_destroy(g);
     return fail(from_hip(e), std::string("graph upload: ") + hipGetErrorString(e));

@@ -68,6 +68,12 @@ struct sssp_graph {
   sssp_impl::DevBuf edges;  // uint64[m]: (weight << 32) | internal target
   sssp_impl::DevBuf perm, inv;
   bool relabelled = false;
+  // SSSP_BORROW_DEVICE: the caller's device targets and weights are used in
+  // place (edges is then empty; the caller keeps them alive and unchanged
+  // in shape until the graph is destroyed).
+  bool borrowed = false;
+  const int32_t* btgt = nullptr;
+  const uint32_t* bwt = nullptr;
   bool undirected = false;  // every arc (u, v, w) has its reverse (v, u, w)
   bool serving = false;  // a persistent server owns the workspace
   void* pending = nullptr;          // the pending asynchronous solve (owned by stepping.hip)
@@ -80,18 +86,24 @@ struct sssp_graph {
   uint64_t ws_src_cap = 0;  // sources the `srcs` buffer holds
   uint64_t ws_segcap = 0;   // F entries per workgroup the workspace was sized for
   uint32_t ws_local_cap = 0;  // local-expansion degree cap of bigmask
+  bool ws_repeat = false;     // lastkey / ckey / cbase allocated (repeated-push skip)
+  uint64_t nhub = 0;          // hubs numbered first (entries of cbase), with ws_repeat on a relabelled graph
   sssp_impl::DevBuf dist_int, bitmap, hint, tree, hubmask, bigmask, F, FD, H, L, samples, parts, ctl, args, srcs;
+  sssp_impl::DevBuf lastkey, ckey, cbase;
   void* hargs = nullptr;  // host staging copy of the kernel arguments (operator new)
 
   uint64_t graph_bytes() const { return off.bytes + edges.bytes + perm.bytes + inv.bytes; }
   uint64_t workspace_bytes() const {
     return dist_int.bytes + bitmap.bytes + hint.bytes + tree.bytes + hubmask.bytes + bigmask.bytes + F.bytes + FD.bytes + H.bytes + L.bytes + samples.bytes +
-           parts.bytes + ctl.bytes + args.bytes + srcs.bytes;
+           parts.bytes + ctl.bytes + args.bytes + srcs.bytes + lastkey.bytes + ckey.bytes + cbase.bytes;
   }
   void release_ws(hipStream_t st) {
-    for (sssp_impl::DevBuf* b : {&dist_int, &bitmap, &hint, &tree, &hubmask, &bigmask, &F, &FD, &H, &L, &samples, &parts, &ctl, &args, &srcs})
+    for (sssp_impl::DevBuf* b : {&dist_int, &bitmap, &hint, &tree, &hubmask, &bigmask, &F, &FD, &H, &L, &samples, &parts, &ctl, &args, &srcs,
+                                 &lastkey, &ckey, &cbase})
       b->release(st);
     ws_ready = false;
+    ws_repeat = false;
+    nhub = 0;
     ws_src_cap = 0;
   }
   void release_all() {

@@ -76,6 +76,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "hint_code.h"
 #include "internal.h"
 
 using namespace sssp_impl;
@@ -88,6 +89,8 @@ constexpr int UNROLL = 4;       // arcs / list entries per lane per iteration
 constexpr int BATCH = 4;        // queue members per lane per round in bitmap scans
 constexpr int MAX_XCC = 16;
 constexpr int BLOCK_WORDS = 4;  // bitmap words per ownership block (256 vertices)
+// The word-per-wave Extract gives wave w word w of each block it owns.
+static_assert(BLOCK_WORDS == WAVES, "one wave per bitmap word of a block");
 constexpr int LQ = 1024;        // local-expansion list capacity per round (LDS)
 
 // ---------------------------------------------------------------------------
@@ -119,7 +122,7 @@ struct TeamCtl {
   ull query;   // index of the source being solved
   ull status;  // 1: step limit reached on some query
   ull st_steps, st_extracted, st_edges, st_success, st_dense, st_sampled;
-  ull st_qdense, st_qlist, st_appends, st_local;
+  ull st_qdense, st_qlist, st_appends, st_local, st_skipped;
   ull relax_busy_max, relax_busy_sum;
   ull phase_ticks[4];  // init, threshold, extract, relax (the team's first workgroup)
   // Serving: the current request and the one still to be published.
@@ -177,6 +180,7 @@ struct alignas(64) Part {
   ull minnew;   // min successful WriteMin value
   ull busy;     // wall-clock ticks this workgroup spent in Relax
   ull local;    // vertices relaxed by local expansion
+  ull skipped;  // arcs not pushed again: their tail's key had not changed since its last push
 };
 
 struct KArgs {
@@ -184,7 +188,9 @@ struct KArgs {
   uint64_t m;
   uint64_t nwords;
   const int64_t* off;
-  const ull* edges;     // (weight << 32) | target
+  const ull* edges;     // (weight << 32) | target; NULL when the caller's arrays are borrowed:
+  const int32_t* tgt;   // borrowed targets and weights (graphs created with SSSP_BORROW_DEVICE)
+  const uint32_t* wt;
   const ull* hubmask;   // bit v set iff deg(v) > hub_degree
   const ull* bigmask;   // bit v set iff deg(v) > the local-expansion degree cap
   const int32_t* perm;  // internal id -> caller id (NULL: identity)
@@ -194,6 +200,10 @@ struct KArgs {
   ull* dist_int;        // per-team internal rows (relabelled graphs), else NULL
   ull* bitmap;          // per team, nwords
   uint16_t* hint;       // per team, n: upper bound of each key for the Relax filter (NULL: no filter)
+  ull* lastkey;         // per team, n: the key a vertex's arcs were last pushed with (NULL: off)
+  ull* ckey;            // per team, hcap: the same per hub chunk (NULL: off)
+  const uint32_t* cbase;  // hub u < nhub: index of u's first chunk in ckey (hubs are numbered first)
+  uint64_t nhub;
   ull* key1;            // tournament-tree queue (NULL: flat array): per team, nwords (one node per bitmap word)
   ull* key2;            // per team, n2 (one node per 64 words)
   uint64_t n2;
@@ -255,6 +265,8 @@ struct Shared {
   int32_t lq[2][LQ];  // local expansion: this round's vertices and the next round's
   uint32_t lqn[2];
   uint32_t fcnt;  // F entries reserved by this workgroup in a bitmap step
+  ull hub_task, hub_du;  // the hub chunk in hand and the key it is pushed with
+  int hub_skip;
   int last;
   int abort;
 };
@@ -267,6 +279,8 @@ struct Team {
   TeamCtl* ctl;
   ull* bitmap;
   uint16_t* hint;
+  ull* lastkey;  // repeated-push skip (NULL: off)
+  ull* ckey;
   ull* key1;  // tournament tree (NULL: flat array)
   ull* key2;
   ull* H;
@@ -323,6 +337,21 @@ __device__ __forceinline__ ull ld_agent(P p) {
 // pass, so it is marked non-temporal and does not push the keys of
 // frequently relaxed targets out of L2.
 __device__ __forceinline__ ull ld_stream(const ull* p) { return __builtin_nontemporal_load(glob(p)); }
+
+// Arc e as (weight << 32) | target: one 8-byte load from the library's
+// packed arcs, or two 4-byte loads from the caller's borrowed arrays (a
+// uniform branch on the launch's layout).
+struct ArcSrc {
+  const ull* packed;
+  const int32_t* tgt;
+  const uint32_t* wt;
+  __device__ __forceinline__ ull at(ull e) const {
+    if (packed) return ld_stream(packed + e);
+    const uint32_t w = __builtin_nontemporal_load(glob(wt + e));
+    const uint32_t t = (uint32_t)__builtin_nontemporal_load(glob(tgt + e));
+    return ((ull)w << 32) | t;
+  }
+};
 template <class P>
 __device__ __forceinline__ int32_t ld_agent_i32(P p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -649,34 +678,7 @@ __device__ __noinline__ void wave_push_hubs(const KArgs& a, ull* H, StepSlot* S,
 // skipped. This read is the one random read of every arc, and the codes take
 // a quarter of the cache lines of the keys; rounding the bound up lets a few
 // more arcs through to the atomic.
-constexpr uint32_t HINT_NONE = 0xFFFFu;
-
-// The code: below 2048 the value itself; above, exponent e (1..31) in the
-// top 5 bits and m in the low 11, for the value (2048 + m) << (e - 1).
-// Values grow with the code.
-__device__ __forceinline__ ull hint_value(uint32_t c) {
-  const uint32_t e = c >> 11, m = c & 2047u;
-  return e == 0 ? (ull)m : ((ull)(2048u + m) << (e - 1));
-}
-// The smallest code whose value is at least d (HINT_NONE beyond the range).
-__device__ __forceinline__ uint16_t as_hint(ull d) {
-  if (d < 2048) return (uint16_t)d;
-  const int b = 63 - __clzll((long long)d);  // d's top bit, at least 11
-  uint32_t e = (uint32_t)(b - 10);
-  ull mf = d >> (e - 1);  // in [2048, 4095]
-  if ((mf << (e - 1)) < d) ++mf;
-  if (mf == 4096) {
-    ++e;
-    mf = 2048;
-  }
-  const uint32_t c = (e << 11) | (uint32_t)(mf - 2048);
-  return (e > 31 || c >= HINT_NONE) ? (uint16_t)HINT_NONE : (uint16_t)c;
-}
-
-// check = false skips the filter read (the hint is still kept): in
-// super-sparse steps with local expansion the work is a chain of hops, each
-// waiting for the last, so a read before the atomic costs a round trip per
-// hop and saves little.
+// The codes and their values: hint_code.h.
 
 // Update(v) (S4): set v's flag; true when v is new to Q.
 __device__ __forceinline__ bool mark(ull* bitmap, int32_t v) {
@@ -1227,7 +1229,7 @@ __device__ __noinline__ ExtractOut phase_extract_list(const KArgs& a, const ull*
 }
 
 struct RelaxAcc {
-  ull edges, succ, fresh, minnew, local;
+  ull edges, succ, fresh, minnew, local, skipped;
 };
 
 // Local expansion (the paper's large neighbour sets, Sec. 6): in a sparse
@@ -1337,11 +1339,23 @@ __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* 
                                            bool emit, RelaxAcc& acc, const Local& lx, int32_t u, ull du) {
   Shared& sh = g_sh;
   const unsigned tid = threadIdx.x;
+  const ArcSrc arcs{a.edges, a.tgt, a.wt};
   uint32_t deg = 0;
   ull rb = 0;
   if (u >= 0) {
     rb = (ull)*glob(&a.off[u]);
     deg = (uint32_t)((ull)*glob(&a.off[u + 1]) - rb);
+    if (tm.lastkey) {
+      // u's arcs were already pushed with this very key: every WriteMin
+      // would fail, so they are not pushed again.
+      const gptr<ull> lk = glob(tm.lastkey);
+      if (ld_agent(&lk[u]) == du) {
+        acc.skipped += deg;
+        deg = 0;
+      } else {
+        lk[u] = du;
+      }
+    }
   }
   uint32_t total;
   const uint32_t excl = wg_scan(sh, deg, total);
@@ -1362,7 +1376,7 @@ __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* 
 #pragma unroll
           for (int step = WG / 2; step > 0; step >>= 1)
             if (sh.pre[lo + step] <= e) lo += step;
-          const ull arc = a.edges[sh.beg[lo] + (e - sh.pre[lo])];
+          const ull arc = arcs.at(sh.beg[lo] + (e - sh.pre[lo]));
           const ull dv = ld_plain(&dist[(uint32_t)arc]);
           if (dv != INF) {
             const ull cand = dv + (arc >> 32);
@@ -1382,7 +1396,6 @@ __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* 
     }
     __syncthreads();
   }
-  const ull* edges = a.edges;
   for (uint32_t e0 = 0; e0 < total; e0 += WG * UNROLL) {
     ull ev[UNROLL], dd[UNROLL];
 #pragma unroll
@@ -1396,7 +1409,7 @@ __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* 
 #pragma unroll
           for (int step = WG / 2; step > 0; step >>= 1)
             if (sh.pre[lo + step] <= e) lo += step;
-          ev[k] = ld_stream(&edges[sh.beg[lo] + (e - sh.pre[lo])]);
+          ev[k] = arcs.at(sh.beg[lo] + (e - sh.pre[lo]));
           dd[k] = sh.du[lo];
         }
       } else {
@@ -1407,7 +1420,7 @@ __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* 
 #pragma unroll
         for (int step = WG / 2; step > 0; step >>= 1)
           if (sh.pre[lo + step] <= ec) lo += step;
-        const ull arc = ld_stream(&edges[sh.beg[lo] + (ec - sh.pre[lo])]);
+        const ull arc = arcs.at(sh.beg[lo] + (ec - sh.pre[lo]));
         ev[k] = e < total ? arc : INF;
         dd[k] = sh.du[lo];
       }
@@ -1417,36 +1430,60 @@ __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* 
   __syncthreads();
 }
 
-// S3 + S4: the team's hub chunks (strided over its workgroups), then this
-// workgroup's own extracted vertices, then (local expansion) the rounds of
-// vertices they improved. Writes the workgroup's partial counts.
-__device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S, int32_t* Lnext, bool emit,
-                                         ExtractOut ex, bool local, ull theta) {
+// The team's hub chunks, strided over its workgroups. Each chunk is pushed
+// with one key, u's current key read once (or its key at extraction with
+// snapshot keys); a chunk already pushed with that very key (ckey) is
+// skipped, since every WriteMin of it would fail.
+__device__ __noinline__ RelaxAcc relax_hub_chunks(const KArgs& a, ull* dist, StepSlot* S, int32_t* Lnext,
+                                                  bool emit, const Local lx) {
   const Team& tm = g_tm;
   Shared& sh = g_sh;
   const unsigned tid = threadIdx.x;
-  const long long t_start = wall_clock64();
-  RelaxAcc acc{0, 0, 0, INF, 0};
-  Local lx{local, 0, theta};
-  if (tid < 2) sh.lqn[tid] = 0;
-  __syncthreads();
+  // Counts in registers (this function is not inlined: a reference to the
+  // caller's counters would put them in scratch memory).
+  RelaxAcc acc{0, 0, 0, INF, 0, 0};
+  const ArcSrc arcs{a.edges, a.tgt, a.wt};
   const ull nH = ld_agent(&S->h_count);
   const ull CH = a.chunk_edges;
   for (ull item = tm.rank; item < nH; item += tm.T) {
-    const ull task = ld_agent(&tm.H[2 * item]);
+    if (tid == 0) {
+      const ull task = ld_agent(&tm.H[2 * item]);
+      const int32_t u0 = (int32_t)(task >> 32);
+      const ull d0 = a.snapshot ? ld_agent(&tm.H[2 * item + 1]) : ld_agent(&dist[u0]);
+      int skip = 0;
+      if (tm.ckey && (ull)u0 < a.nhub) {
+        ull* ck = &tm.ckey[a.cbase[u0] + (task & 0xffffffffull)];
+        if (ld_agent(ck) == d0) {
+          skip = 1;
+        } else if (!a.pull) {
+          *ck = d0;
+        }
+      }
+      sh.hub_task = task;
+      sh.hub_du = d0;
+      sh.hub_skip = skip;
+    }
+    __syncthreads();
+    const ull task = sh.hub_task;
+    ull du = sh.hub_du;
+    const bool skip = sh.hub_skip != 0;
+    __syncthreads();
     const int32_t u = (int32_t)(task >> 32);
-    ull du = a.snapshot ? ld_agent(&tm.H[2 * item + 1]) : ld_agent(&dist[u]);
     const ull c = task & 0xffffffffull;
     const ull rb = (ull)a.off[u], re = (ull)a.off[u + 1];
     const ull beg = rb + c * CH;
     const ull end = umin(beg + CH, re);
+    if (skip) {
+      if (tid == 0) acc.skipped += end - beg;
+      continue;
+    }
     if (a.pull) {
       // Bidirectional relaxation over this chunk's neighbours. Other chunks
       // of u may already have pushed with the older key, so a lower key
       // also puts u back in Q.
       ull best = du;
       for (ull e = beg + tid; e < end; e += WG) {
-        const ull arc = a.edges[e];
+        const ull arc = arcs.at(e);
         const ull dv = ld_plain(&dist[(uint32_t)arc]);
         if (dv != INF) best = umin(best, dv + (arc >> 32));
       }
@@ -1467,8 +1504,8 @@ __device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S,
         if (emit) list_append(a, S, Lnext, v1, m1);
         du = best;
       }
+      if (tid == 0 && tm.ckey && (ull)u < a.nhub) tm.ckey[a.cbase[u] + c] = du;
     }
-    const ull* edges = a.edges;
     for (ull e0 = beg; e0 < end; e0 += (ull)WG * UNROLL) {
       ull ev[UNROLL], dd[UNROLL];
 #pragma unroll
@@ -1476,12 +1513,36 @@ __device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S,
         // A chunk is never empty; lanes past its end read its last arc and
         // drop it (unconditional reads, in flight together).
         const ull e = e0 + (ull)k * WG + tid;
-        const ull arc = ld_stream(&edges[e < end ? e : end - 1]);
+        const ull arc = arcs.at(e < end ? e : end - 1);
         ev[k] = e < end ? arc : INF;
         dd[k] = du;
       }
       relax_batch(a, tm, dist, S, Lnext, emit, acc, lx, ev, dd);
     }
+  }
+  return acc;
+}
+
+// S3 + S4: the team's hub chunks (strided over its workgroups), then this
+// workgroup's own extracted vertices, then (local expansion) the rounds of
+// vertices they improved. Writes the workgroup's partial counts.
+__device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S, int32_t* Lnext, bool emit,
+                                         ExtractOut ex, bool local, ull theta) {
+  const Team& tm = g_tm;
+  Shared& sh = g_sh;
+  const unsigned tid = threadIdx.x;
+  const long long t_start = wall_clock64();
+  RelaxAcc acc{0, 0, 0, INF, 0, 0};
+  Local lx{local, 0, theta};
+  if (tid < 2) sh.lqn[tid] = 0;
+  __syncthreads();
+  {
+    const RelaxAcc h = relax_hub_chunks(a, dist, S, Lnext, emit, lx);
+    acc.edges += h.edges;
+    acc.succ += h.succ;
+    acc.fresh += h.fresh;
+    acc.minnew = umin(acc.minnew, h.minnew);
+    acc.skipped += h.skipped;
   }
   // Round 0: this workgroup's extracted vertices. Later rounds (local
   // expansion): LDS list `cur`, the vertices the previous round improved
@@ -1537,8 +1598,8 @@ __device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S,
   ull xs = ex.x, mk = ex.minkept;
   wg_reduce4(sh, acc.edges, acc.succ, acc.fresh, acc.minnew);
   {
-    ull z0 = 0, z1 = 0;
-    wg_reduce4(sh, xs, z0, z1, mk);
+    ull z1 = 0;
+    wg_reduce4(sh, xs, acc.skipped, z1, mk);
   }
   if (tid == 0) {
     Part p;
@@ -1550,6 +1611,7 @@ __device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S,
     p.minnew = acc.minnew;
     p.busy = (ull)(wall_clock64() - t_start);
     p.local = acc.local;
+    p.skipped = acc.skipped;
     a.parts[blockIdx.x] = p;
   }
 }
@@ -1657,7 +1719,7 @@ __device__ __noinline__ void step_bookkeeping(const KArgs& a, StepSlot* S, ull t
   Shared& sh = g_sh;
   const unsigned tid = threadIdx.x;
   TeamCtl* tc = tm.ctl;
-  ull x = 0, e = 0, s = 0, f = 0, mn = INF, busy = 0, negbusy = INF, lv = 0;
+  ull x = 0, e = 0, s = 0, f = 0, mn = INF, busy = 0, negbusy = INF, lv = 0, sk = 0;
   for (ull r = tid; r < tm.T; r += WG) {
     // Group rank r is rank r % Tteam of member team r / Tteam.
     const ull team = tm.k > 1 ? (ull)ld_agent_i32(&tc->gteam[r / tm.Tteam]) : tm.id;
@@ -1670,11 +1732,16 @@ __device__ __noinline__ void step_bookkeeping(const KArgs& a, StepSlot* S, ull t
     mn = umin(mn, ld_agent(p + 5));
     const ull bz = ld_agent(p + 6);
     lv += ld_agent(p + 7);
+    sk += ld_agent(p + 8);
     busy += bz;
     negbusy = umin(negbusy, ~bz);
   }
   wg_reduce4(sh, x, e, s, mn);
   wg_reduce4(sh, f, busy, lv, negbusy);
+  {
+    ull z0 = 0, z1 = 0, z2 = INF;
+    wg_reduce4(sh, sk, z0, z1, z2);
+  }
   if (tid < 16) {
     ull* z = reinterpret_cast<ull*>(&tc->slot[(t + 2) % 3]);
     z[tid] = 0ull;
@@ -1691,6 +1758,7 @@ __device__ __noinline__ void step_bookkeeping(const KArgs& a, StepSlot* S, ull t
     S->successes = s;
     S->local_v = lv;
     tc->st_local += lv;
+    tc->st_skipped += sk;
     tc->st_steps += 1;
     tc->st_extracted += x;
     tc->st_edges += e;
@@ -1897,6 +1965,8 @@ __device__ __forceinline__ void bind_workspace(const KArgs& a, Team& tm, ull t) 
   tm.ctl = a.teams + t;
   tm.bitmap = a.bitmap + t * a.nwords;
   tm.hint = a.hint ? a.hint + t * (ull)a.n : nullptr;
+  tm.lastkey = a.lastkey ? a.lastkey + t * (ull)a.n : nullptr;
+  tm.ckey = a.ckey ? a.ckey + t * a.hcap : nullptr;
   tm.key1 = a.key1 ? a.key1 + t * a.nwords : nullptr;
   tm.key2 = a.key1 ? a.key2 + t * a.n2 : nullptr;
   tm.H = a.H + t * 2 * a.hcap;
@@ -2030,6 +2100,10 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
     for (ull i = tm.rank * WG + tid; i < n; i += tm.T * WG) dist[i] = INF;
     if (tm.hint)
       for (ull i = tm.rank * WG + tid; i < n; i += tm.T * WG) tm.hint[i] = HINT_NONE;
+    if (tm.lastkey)
+      for (ull i = tm.rank * WG + tid; i < n; i += tm.T * WG) tm.lastkey[i] = INF;
+    if (tm.ckey)
+      for (ull i = tm.rank * WG + tid; i < a.hcap; i += tm.T * WG) tm.ckey[i] = INF;
     if (tm.key1) {
       for (ull i = tm.rank * WG + tid; i < a.nwords; i += tm.T * WG) tm.key1[i] = INF;
       for (ull i = tm.rank * WG + tid; i < a.n2; i += tm.T * WG) tm.key2[i] = INF;
@@ -2059,6 +2133,15 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
     }
 
     ull q = 1, minq = 0, idelta = 0, large_steps = 0;
+    // Serving groups: rho and Delta are given per team, so a group of k
+    // teams extracts k times as much per step (its work per step grows with
+    // its workgroups; a lone team with the group's parameters would take
+    // many serial hops per step).
+    ull rho = a.rho, delta = a.delta;
+    if (a.serve) {
+      if (__builtin_mul_overflow(a.rho, tm.k, &rho)) rho = INF;
+      if (__builtin_mul_overflow(a.delta, tm.k, &delta)) delta = INF;
+    }
     // Vertices relaxed and arcs of the previous step (before the first: the
     // whole graph, so that the first step is super-sparse when the graph is).
     ull prev_x = n, prev_e = a.m;
@@ -2086,18 +2169,18 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
         theta = minq;
       } else if (a.rule == SSSP_RULE_DELTA_STAR) {
         ull i = idelta + 1;
-        const ull skip = minq / a.delta + (minq % a.delta != 0);  // ceil(min / Delta)
+        const ull skip = minq / delta + (minq % delta != 0);  // ceil(min / Delta)
         if (skip > i) i = skip;
         idelta = i;
         ull prod;
-        theta = __builtin_mul_overflow(i, (ull)a.delta, &prod) ? INF : prod;
+        theta = __builtin_mul_overflow(i, delta, &prod) ? INF : prod;
       } else if (a.rule == SSSP_RULE_RHO_EXACT) {
-        if (q > a.rho) {
+        if (q > rho) {
           // Exact rho-th smallest key: a bounds pass, then 8-bit digit passes.
           exact = true;
           phase_select(a, dist, Lcur, q, dense, true, 64, 0, 0, 0);
           auto start = [&]() {
-            if (tid == 0) select_serial(tm.ctl, true, 0, a.rho);
+            if (tid == 0) select_serial(tm.ctl, true, 0, rho);
           };
           if (!team_sync(a, sh, tm, start)) return;
           int top = (int)ld_agent(&tm.ctl->sel_top);
@@ -2119,8 +2202,8 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
         // The first two steps whose queue exceeds rho / 10 use rho / 10 (Sec. 6
         // lowers rho for the first large steps, whose threshold estimates are
         // the least accurate).
-        const ull rho10 = (a.rho / 10) > 0 ? a.rho / 10 : 1;
-        const ull rho_eff = large_steps < 2 ? rho10 : a.rho;
+        const ull rho10 = (rho / 10) > 0 ? rho / 10 : 1;
+        const ull rho_eff = large_steps < 2 ? rho10 : rho;
         if (q > rho10) ++large_steps;
         if (q > rho_eff) {
           sampled = true;
@@ -2226,6 +2309,48 @@ __global__ void hubmask_kernel(const int64_t* off, ull n, ull nwords, uint32_t h
   }
 }
 
+// First chunk index of every hub (out-degree above hub_degree) in the
+// per-chunk key array: an exclusive prefix sum of ceil(degree / chunk) over
+// the hubs, which a graph numbered by decreasing degree holds first. One
+// workgroup of 1024 threads; stops at the first block holding a vertex that
+// is not a hub, and writes the hub count to *nhub.
+__global__ __launch_bounds__(1024) void chunk_base_kernel(const int64_t* off, ull n, uint32_t hub_degree,
+                                                         uint32_t chunk, uint32_t* cbase, ull* nhub) {
+  __shared__ uint32_t wsum[16];
+  __shared__ int any_small;
+  const unsigned tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t base = 0;
+  ull hubs = 0;
+  for (ull b0 = 0; b0 < n; b0 += 1024) {
+    const ull v = b0 + tid;
+    const ull deg = v < n ? (ull)(off[v + 1] - off[v]) : 0;
+    const bool is_hub = v < n && deg > hub_degree;
+    const uint32_t c = is_hub ? (uint32_t)((deg + chunk - 1) / chunk) : 0u;
+    uint32_t incl = c;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o);
+      if ((int)lane >= o) incl += y;
+    }
+    if (tid == 0) any_small = 0;
+    __syncthreads();
+    if (lane == 63) wsum[wave] = incl;
+    if (v < n && !is_hub) any_small = 1;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (unsigned w = 0; w < 16; ++w) {
+      before += w < wave ? wsum[w] : 0u;
+      total += wsum[w];
+    }
+    if (is_hub) cbase[v] = base + before + incl - c;
+    base += total;
+    const int stop = any_small;
+    ull cnt = is_hub ? 1 : 0;
+    hubs += (ull)__syncthreads_count((int)cnt);
+    if (stop) break;
+  }
+  if (tid == 0) *nhub = hubs;
+}
+
 // Zero the control blocks before a solve (a kernel rather than a memset, so
 // the sequence stays valid under stream capture).
 __global__ void reset_control_kernel(ull* p, ull words) {
@@ -2239,7 +2364,7 @@ sssp_tuning default_tuning() {
   t.hub_degree = 1024;
   t.chunk_edges = 4096;
   t.list_divisor = 64;
-  t.sample_cap = 4096;
+  t.sample_cap = 1u << 16;
   t.probe_cap = 1u << 16;
   t.no_filter = 0;
   t.teams = 0;
@@ -2351,10 +2476,11 @@ hipError_t build_masks(const sssp_graph* g, const sssp_tuning& tu, const Geometr
   return hipGetLastError();
 }
 
-sssp_status ensure_workspace(sssp_graph* g, const sssp_tuning& tu, const Geometry& geo, hipStream_t st) {
+sssp_status ensure_workspace(sssp_graph* g, const sssp_tuning& tu, const Geometry& geo, bool repeat,
+                             hipStream_t st) {
   if (g->ws_ready && g->ws_hub_degree == tu.hub_degree && g->ws_chunk == tu.chunk_edges &&
       g->ws_probe_cap >= tu.probe_cap && g->ws_G == geo.G && g->ws_teams == geo.nteams && g->ws_segcap == geo.segcap &&
-      g->ws_local_cap == local_degree_cap(tu))
+      g->ws_local_cap == local_degree_cap(tu) && g->ws_repeat == repeat)
     return SSSP_OK;
   g->release_ws(st);
   const uint64_t n = (uint64_t)g->n, nt = geo.nteams;
@@ -2377,6 +2503,26 @@ sssp_status ensure_workspace(sssp_graph* g, const sssp_tuning& tu, const Geometr
     if (!g->hargs) return fail(SSSP_ERR_OUT_OF_MEMORY, "kernel argument staging");
   }
   SSSP_HIP_TRY(build_masks(g, tu, geo, g->hubmask.p, g->bigmask.p, st));
+  if (repeat) {
+    SSSP_HIP_TRY(g->lastkey.alloc(nt * n * 8, st));
+    if (g->relabelled) {
+      // Hub chunks have keys of their own; hubs are numbered first.
+      SSSP_HIP_TRY(g->ckey.alloc(nt * geo.hcap * 8, st));
+      // nhub <= m / (hub_degree + 1) entries, then the hub count (8-byte aligned).
+      const uint64_t cb_bytes = ((uint64_t)g->m / ((uint64_t)tu.hub_degree + 1) + 2) * 4;
+      const uint64_t cnt_off = (cb_bytes + 7) / 8 * 8;
+      SSSP_HIP_TRY(g->cbase.alloc(cnt_off + 8, st));
+      uint64_t* cnt = reinterpret_cast<uint64_t*>((char*)g->cbase.p + cnt_off);
+      chunk_base_kernel<<<1, 1024, 0, st>>>((const int64_t*)g->off.p, n, tu.hub_degree, tu.chunk_edges,
+                                            (uint32_t*)g->cbase.p, (ull*)cnt);
+      SSSP_HIP_TRY(hipGetLastError());
+      uint64_t nh = 0;
+      SSSP_HIP_TRY(hipMemcpyAsync(&nh, cnt, 8, hipMemcpyDeviceToHost, st));
+      SSSP_HIP_TRY(hipStreamSynchronize(st));
+      g->nhub = nh;
+    }
+  }
+  g->ws_repeat = repeat;
   g->ws_ready = true;
   g->ws_hub_degree = tu.hub_degree;
   g->ws_chunk = tu.chunk_edges;
@@ -2461,7 +2607,9 @@ void fill_args(const sssp_graph* g, Launch& L, const WsView& w, uint64_t* dist) 
   a.m = (uint64_t)g->m;
   a.nwords = geo.nwords;
   a.off = (const int64_t*)g->off.p;
-  a.edges = (const ull*)g->edges.p;
+  a.edges = g->borrowed ? nullptr : (const ull*)g->edges.p;
+  a.tgt = g->btgt;
+  a.wt = g->bwt;
   a.perm = g->relabelled ? (const int32_t*)g->perm.p : nullptr;
   a.inv = g->relabelled ? (const int32_t*)g->inv.p : nullptr;
   a.dist_out = (ull*)dist;
@@ -2526,9 +2674,25 @@ void fill_args(const sssp_graph* g, Launch& L, const WsView& w, uint64_t* dist) 
 sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uint64_t* dist, hipStream_t st) {
   sssp_status s = plan_launch(g, L, default_teams);
   if (s != SSSP_OK) return s;
-  s = ensure_workspace(g, L.tu, L.geo, st);
+  // Repeated-push skip: by default for launches of one team (its arrays
+  // cost 8 bytes per vertex and per hub chunk for every team) on graphs
+  // without local expansion (average out-degree at least the super-sparse
+  // threshold): there, repeated pushes of high-degree vertices are common;
+  // on sparse graphs the extra read per vertex cost more than it saved.
+  const bool dense_graph = (uint64_t)g->m >= (uint64_t)L.tu.super_sparse_degree * (uint64_t)g->n;
+  const bool repeat = L.tu.repeat_skip != 0xFFFFFFFFu &&
+                      (L.tu.repeat_skip == 1 || (L.nteams == 1 && dense_graph));
+  s = ensure_workspace(g, L.tu, L.geo, repeat, st);
   if (s != SSSP_OK) return s;
   fill_args(g, L, graph_view(g), dist);
+  if (repeat) {
+    L.a.lastkey = (ull*)g->lastkey.p;
+    if (g->relabelled && g->nhub > 0) {
+      L.a.ckey = (ull*)g->ckey.p;
+      L.a.cbase = (const uint32_t*)g->cbase.p;
+      L.a.nhub = g->nhub;
+    }
+  }
   return SSSP_OK;
 }
 
@@ -2580,6 +2744,7 @@ sssp_status collect_stats(sssp_graph* g, const Launch& L, const void* ctl_dev, h
     stats->queue_list += tc.st_qlist;
     stats->list_appends += tc.st_appends;
     stats->local_vertices += tc.st_local;
+    stats->repeat_skipped += tc.st_skipped;
     if (t == 0) {
       for (int k = 0; k < 4; ++k) stats->phase_ms[k] = (double)tc.phase_ticks[k] / (double)g->tick_khz;
       stats->relax_wg_ms[0] = (double)tc.relax_busy_max / (double)g->tick_khz;

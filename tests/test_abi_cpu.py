@@ -14,8 +14,8 @@ from paper_2105_06145_amd import _native as N
 HEADER = N.HEADER
 
 
-def declared_functions():
-    text = open(HEADER).read()
+def declared_functions(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(sssp_[a-z_0-9]+)\s*\(", text)))
 
@@ -23,8 +23,15 @@ def declared_functions():
 def test_library_exports_every_declared_symbol():
     names = declared_functions()
     assert {"sssp_graph_create", "sssp_graph_destroy", "sssp_solve", "sssp_status_string",
-            "sssp_last_error", "sssp_default_params", "sssp_graph_info", "sssp_abi_version"} <= set(names)
+            "sssp_last_error", "sssp_default_params", "sssp_graph_info", "sssp_abi_version",
+            "sssp_solve_noalloc", "sssp_server_start_budget"} <= set(names)
     lib = ctypes.CDLL(N.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    # The memory-ceiling microbenchmarks' library and header.
+    names = declared_functions(N.CEIL_HEADER)
+    assert names == ["sssp_ceiling_atomic_min64", "sssp_ceiling_gather16"]
+    lib = ctypes.CDLL(N.CEIL_LIB_PATH)
     for name in names:
         assert hasattr(lib, name), name
 
@@ -51,7 +58,7 @@ def test_struct_layouts_match_header(tmp_path):
 
 
 def test_version_strings_defaults():
-    assert N.sssp_abi_version() == 2
+    assert N.sssp_abi_version() == 3
     assert N.sssp_status_string(N.SSSP_OK) == "ok"
     assert "argument" in N.sssp_status_string(N.SSSP_ERR_INVALID_ARGUMENT)
     assert N.sssp_status_string(99) == "unknown status"
@@ -189,3 +196,12 @@ def test_noalloc_solve_null_arguments_and_limit():
     text = open(HEADER).read()
     m = re.search(r"#define SSSP_NOALLOC_SCRATCH_BYTES \((\d+)ull << (\d+)\)", text)
     assert m and int(m.group(1)) << int(m.group(2)) == N.SSSP_NOALLOC_SCRATCH_BYTES
+
+
+def test_borrow_needs_device_input():
+    off = np.array([0, 1, 2], dtype=np.int64)
+    tgt = np.array([1, 0], dtype=np.int32)
+    w = np.array([3, 3], dtype=np.uint32)
+    rc, h = _create(2, 2, off, tgt, w, N.SSSP_INPUT_HOST | N.SSSP_BORROW_DEVICE)
+    assert rc == N.SSSP_ERR_INVALID_ARGUMENT and h is None
+    assert "BORROW" in N.sssp_last_error()

@@ -650,3 +650,109 @@ def test_full_knn10000_batched_rows(sp):
         for i, s in enumerate(w.sources):
             assert oracle.certificate(g.offsets, g.targets, g.weights, int(s), got[i]) == (0, -1), (rule, i)
     G.close()
+
+
+@pytest.mark.parametrize("teams", [1, 8])
+def test_repeat_skip_keeps_distances(sp, teams):
+    """Pushes skipped because the tail's key has not changed since its last
+    push (per vertex, and per hub chunk with small hub rows and chunks) leave
+    every distance as the oracle's, and on a graph where keys do repeat some
+    arcs are skipped."""
+    g = graphgen.rmat(14, 16, seed=81)
+    srcs = [3, 4000, 11111]
+    exp = [ref(g, s) for s in srcs]
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+    try:
+        skipped_any = 0
+        for rule, kw in (("rho", {"rho": 64}), ("rho", {"rho": 2048}), ("delta", {"delta": 5000}), ("bf", {})):
+            for tun in ({"hub_degree": 64, "chunk_edges": 64}, {}):
+                on = {**tun, "repeat_skip": 1, "teams": teams}
+                off = {**tun, "repeat_skip": 0xFFFFFFFF, "teams": teams}
+                d_on, st_on = sp.solve(G, srcs, rule=rule, tuning=on, **kw)
+                d_off, st_off = sp.solve(G, srcs, rule=rule, tuning=off, **kw)
+                got_on, got_off = sp.to_numpy_u64(d_on), sp.to_numpy_u64(d_off)
+                for i in range(len(srcs)):
+                    assert_same(got_on[i], exp[i], f"{rule} {kw} {on} source {srcs[i]}")
+                    assert_same(got_off[i], exp[i], f"{rule} {kw} {off} source {srcs[i]}")
+                assert st_off["repeat_skipped"] == 0
+                skipped_any += st_on["repeat_skipped"]
+        assert skipped_any > 0
+    finally:
+        G.close()
+
+
+def test_sampled_steps_draw_appendix_b_sample_size(sp):
+    """rho-stepping draws App. B's sample size s = ceil(10 (q / rho' + log q))
+    (log q = 1 + log2(q + 1)) in every sampled step: exactly s from the
+    explicit list, and from the bitmap about 1.25 s n / q probes of which
+    the queued ones are kept (their count near probes * q / n, at least s on
+    average). rho' is rho / 10 in the first two steps whose queue exceeds
+    rho / 10 (Sec. 6), else rho."""
+    import math
+    g = graphgen.rmat(16, 16, seed=83)
+    n = g.n
+    src = int(graphgen.pick_sources(n, 1, 84, graphgen.largest_component(g))[0])
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+    try:
+        checked = 0
+        for rho in (64, 512, 4096):
+            d, st = sp.solve(G, [src], rule="rho", rho=rho, trace=4096)
+            assert_same(sp.to_numpy_u64(d)[0], ref(g, src), f"rho {rho}")
+            rho10 = max(1, rho // 10)
+            large = 0
+            for r in st["trace"]:
+                q = r["q"]
+                rho_eff = rho10 if large < 2 else rho
+                if q > rho10:
+                    large += 1
+                sampled = bool(r["flags"] & 4)
+                assert sampled == (q > rho_eff), (rho, r)
+                if not sampled:
+                    continue
+                s = math.ceil(10.0 * (q / rho_eff + 1.0 + math.log2(q + 1.0)))
+                if r["flags"] & 1:  # bitmap step: rejection probing
+                    probes = min(1 << 16, math.ceil(s * n / q * 1.25))
+                    mean = probes * q / n
+                    if probes < (1 << 16):
+                        assert mean >= s
+                    assert abs(r["samples"] - mean) <= 6 * math.sqrt(mean) + 1, (rho, q, s, r["samples"], mean)
+                else:  # explicit list: exactly s samples
+                    assert r["samples"] == min(s, 1 << 16), (rho, q, s, r["samples"])
+                checked += 1
+        assert checked > 10
+    finally:
+        G.close()
+
+
+def test_borrowed_device_arrays_are_used_in_place(sp, torch_cuda):
+    """SSSP_BORROW_DEVICE: the caller's device targets and weights are read in
+    place (no packed copy): distances match the oracle, the graph holds no
+    arc storage of its own, and weights changed in the caller's tensor are
+    the weights of the next solve."""
+    torch = torch_cuda
+    g = graphgen.rmat(13, 16, seed=85)
+    off = torch.from_numpy(g.offsets.astype(np.int64)).cuda()
+    tgt = torch.from_numpy(g.targets.astype(np.int32)).cuda()
+    w = torch.from_numpy(g.weights.view(np.int32).copy()).cuda()
+    srcs = [0, 17, 4000]
+    for undirected, tun in ((False, None), (True, {"pull": 1})):
+        G = sp.Graph.from_csr(off, tgt, w, borrow=True, undirected=undirected)
+        copied = sp.Graph.from_csr(off, tgt, w, reorder=False)
+        try:
+            # Graph storage: offsets only, against offsets and 8-byte arcs.
+            assert G.device_bytes() == 8 * (g.n + 1)
+            assert copied.device_bytes() == 8 * (g.n + 1) + 8 * g.m
+            d, _ = sp.solve(G, srcs, rule="rho", rho=256, tuning=tun)
+            got = sp.to_numpy_u64(d)
+            for i, s in enumerate(srcs):
+                assert_same(got[i], ref(g, s), f"borrowed, source {s}")
+            w.mul_(3)  # in place, both arcs of a pair alike
+            d, _ = sp.solve(G, srcs, rule="delta", delta=3000, tuning=tun)
+            got = sp.to_numpy_u64(d)
+            w3 = g.weights * np.uint32(3)
+            for i, s in enumerate(srcs):
+                assert_same(got[i], oracle.dijkstra(g.offsets, g.targets, w3, s), f"weights x3, source {s}")
+            w.div_(3, rounding_mode="floor")
+        finally:
+            G.close()
+            copied.close()
