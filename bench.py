@@ -417,6 +417,8 @@ def run_knn_compare(args, torch, sp):
     res = {k: r[k] for k in keep}
     res["config"] = {k: r["config"][k] for k in ("n", "m", "queries", "rule", "delta", "teams")}
     res["workload"] = WORKLOADS["knn10000"]
+    res["settings"] = ("fixed, from an earlier tuning run of this workload: Delta*-stepping with Delta = 1898 "
+                       "for the batch, 3796 for the single launches")
     return res
 
 
@@ -775,11 +777,11 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=16.0,
                     help="serving: device-memory admission budget (GiB), split between the servers in "
                          "proportion to their grids")
-    ap.add_argument("--serve-bpc", default="3,1",
+    ap.add_argument("--serve-bpc", default="2,2",
                     help="serving: workgroups per CU of the R-MAT and grid servers (sum at most 4)")
-    ap.add_argument("--serve-teams", default="32,16",
-                    help="serving: teams of the R-MAT and grid servers (with --serve-bpc 3,1 on 256 CUs: 32 "
-                         "R-MAT teams of 24 workgroups, 16 grid teams of 16); a request takes a group of "
+    ap.add_argument("--serve-teams", default="16,32",
+                    help="serving: teams of the R-MAT and grid servers (with --serve-bpc 2,2 on 256 CUs: 16 "
+                         "R-MAT teams of 32 workgroups, 32 grid teams of 16); a request takes a group of "
                          "idle teams, all of them when it is alone")
     ap.add_argument("--serve-rho", type=int, default=0,
                     help="serving: the R-MAT server's rho per team (0 = 2^17 / its teams)")
