@@ -290,7 +290,11 @@ struct Team {
   ull* FDb;     // and their keys at extraction
   ull k, Tteam;  // teams working on the current source and workgroups per team (T = k * Tteam)
   ull own;       // this workgroup's own team (serving groups: tm.id is the group's leader)
-  // barrier
+};
+
+// A workgroup's barrier state, the only team state the kernel keeps in
+// registers across its phases (the rest is read from the LDS copy g_tm).
+struct Bar {
   ull epoch;      // first-level barriers passed
   ull l2_epoch;   // second-level barriers passed since l2_base was taken
   ull l2_base;    // second-level arrival count when the current group formed
@@ -520,7 +524,7 @@ __device__ bool flat_sync(const KArgs& a, Shared& sh, Serial serial) {
 
 // Team barrier (see the file comment).
 template <class Serial>
-__device__ bool team_sync(const KArgs& a, Shared& sh, Team& tm, Serial serial) {
+__device__ bool team_sync(const KArgs& a, Shared& sh, Bar& tm, Serial serial) {
   __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached L2
   __syncthreads();
   ++tm.epoch;
@@ -1977,6 +1981,106 @@ __device__ __forceinline__ void bind_workspace(const KArgs& a, Team& tm, ull t) 
 // ---------------------------------------------------------------------------
 // The persistent kernel.
 
+// S0 over the team's share: delta = inf, key bounds unknown, queue empty.
+__device__ __noinline__ void phase_init(const KArgs& a, ull* dist) {
+  const Team& tm = g_tm;
+  const unsigned tid = threadIdx.x;
+  const ull n = (ull)a.n, first = tm.rank * WG + tid, stride = tm.T * WG;
+  for (ull i = first; i < n; i += stride) dist[i] = INF;
+  if (tm.hint)
+    for (ull i = first; i < n; i += stride) tm.hint[i] = HINT_NONE;
+  if (tm.lastkey)
+    for (ull i = first; i < n; i += stride) tm.lastkey[i] = INF;
+  if (tm.ckey)
+    for (ull i = first; i < a.hcap; i += stride) tm.ckey[i] = INF;
+  if (tm.key1) {
+    for (ull i = first; i < a.nwords; i += stride) tm.key1[i] = INF;
+    for (ull i = first; i < a.n2; i += stride) tm.key2[i] = INF;
+  }
+  for (ull i = first; i < a.nwords; i += stride) tm.bitmap[i] = 0;
+}
+
+// Serial part of the init barrier: clear the step slots and selection state,
+// then delta[s] = 0 and Update(s).
+__device__ __noinline__ void seed_source(const KArgs& a, ull* dist, ull qi) {
+  const Team& tm = g_tm;
+  const unsigned tid = threadIdx.x;
+  if (tid < 48) reinterpret_cast<ull*>(&tm.ctl->slot[0])[tid] = 0ull;
+  tm.ctl->sel_hist[tid] = 0;
+  if (tid == 0) {
+    tm.ctl->sel_min = INF;
+    tm.ctl->sel_max = INF;
+    const int32_t src = a.serve ? (int32_t)tm.ctl->src : a.srcs[qi];
+    const int32_t s = a.inv ? a.inv[src] : src;
+    dist[s] = 0;
+    if (tm.hint) tm.hint[s] = 0;
+    if (tm.key1) {
+      tm.key1[s >> 6] = 0;
+      tm.key2[s >> 12] = 0;
+    }
+    tm.bitmap[s >> 6] = 1ull << (s & 63);
+    tm.L[0] = s;
+  }
+}
+
+// Distances back in the caller's vertex ids, and the row checksum added to
+// the team's accumulator.
+__device__ __noinline__ void phase_copyout(const KArgs& a, const ull* dist, ull* out) {
+  const Team& tm = g_tm;
+  const unsigned tid = threadIdx.x;
+  const ull n = (ull)a.n;
+  ull h = 0;
+  if (a.dist_int) {
+    for (ull v = tm.rank * WG + tid; v < n; v += tm.T * WG) {
+      const ull d = ld_agent(&dist[a.inv[v]]);
+      out[v] = d;
+      if (a.hash) h += row_mix(v, d);
+    }
+  } else if (a.hash) {
+    for (ull v = tm.rank * WG + tid; v < n; v += tm.T * WG) h += row_mix(v, ld_agent(&out[v]));
+  }
+  if (a.hash) {
+    h = wave_sum(h);
+    if (lane_id() == 0) atom_add(&tm.ctl->hash_acc, h);
+  }
+}
+
+// Serving: join the group of this team's new assignment (leader's workspace,
+// group ranks in g_tm). Whole workgroup. Returns the group barrier's second
+// level (by value: a reference to the kernel's barrier state would keep it
+// in scratch memory), or ok = false when the team is to leave.
+struct Join {
+  bool ok;
+  ull* l2_arrive;
+  ull* l2_gen;
+  ull l2_size, l2_base;
+};
+
+__device__ __noinline__ Join serve_join(const KArgs& a, bool grouped) {
+  Team tm = g_tm;
+  const TeamCtl* mine = a.teams + tm.own;
+  const bool leave = ld_agent(&mine->mb_exit) != 0;
+  Join br{!leave, nullptr, nullptr, 0, 0};
+  if (!leave) {
+    const ull own_rank = (ull)blockIdx.x / a.nteams;
+    const ull leader = ld_agent(&mine->mb_leader);
+    tm.k = ld_agent(&mine->mb_k);
+    tm.T = tm.k * tm.Tteam;
+    tm.rank = ld_agent(&mine->mb_idx) * tm.Tteam + own_rank;
+    bind_workspace(a, tm, leader);
+    if (grouped && tm.k > 1) {
+      br.l2_arrive = &tm.ctl->garrive.v;
+      br.l2_gen = &tm.ctl->ggen.v;
+      br.l2_size = tm.k;
+      br.l2_base = ld_agent(&mine->mb_base);
+    }
+  }
+  __syncthreads();
+  if (!leave && threadIdx.x == 0) g_tm = tm;
+  __syncthreads();
+  return br;
+}
+
 __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict__ A) {
   Shared& sh = g_sh;
   const KArgs& a = *A;
@@ -1985,21 +2089,26 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
   const ull n = (ull)a.n;
   GridCtl* gc = a.grid;
   const unsigned xcc = __builtin_amdgcn_s_getreg(20 | (15 << 11)) & (MAX_XCC - 1);  // hwreg XCC_ID
-
-  Team tm;
-  const ull own_rank = b / a.nteams;
-  tm.own = b % a.nteams;
-  tm.rank = own_rank;
-  tm.Tteam = a.G / a.nteams;
-  tm.T = tm.Tteam;
-  tm.k = 1;
-  bind_workspace(a, tm, tm.own);
-  tm.Fb = a.F + b * a.segcap;
-  tm.FDb = a.FD + b * a.segcap;
-  tm.epoch = 0;
-  tm.l2_epoch = 0;
-  tm.l2_base = 0;
-  ull* dist = nullptr;
+  const ull own_rank = b / a.nteams, own = b % a.nteams;
+  // The team's state lives in LDS (g_tm), read where it is needed; only the
+  // barrier state stays in registers across the phases.
+  const Team& tm = g_tm;
+  if (tid == 0) {
+    Team t0;
+    t0.own = own;
+    t0.rank = own_rank;
+    t0.Tteam = a.G / a.nteams;
+    t0.T = t0.Tteam;
+    t0.k = 1;
+    bind_workspace(a, t0, own);
+    t0.Fb = a.F + b * a.segcap;
+    t0.FDb = a.FD + b * a.segcap;
+    g_tm = t0;
+  }
+  Bar br;
+  br.epoch = 0;
+  br.l2_epoch = 0;
+  br.l2_base = 0;
   // Serving with several teams: each request is solved by a group of teams
   // (see serve_dispatch); a team alone meets on its own barrier only.
   const bool grouped = a.serve && a.nteams > 1;
@@ -2031,57 +2140,49 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
     if (!flat_sync(a, sh, count_groups)) return;
   }
   if (a.nteams == 1) {
-    tm.l1_arrive = &gc->grp_arrive[xcc].v;
-    tm.l1_gen = &gc->grp_gen[xcc].v;
-    tm.l1_size = ld_agent(&gc->grp_size[xcc].v);
-    tm.l2_arrive = &gc->arrive.v;
-    tm.l2_gen = &gc->gen.v;
-    tm.l2_size = ld_agent(&gc->ngroups);
-    tm.member_release = false;
+    br.l1_arrive = &gc->grp_arrive[xcc].v;
+    br.l1_gen = &gc->grp_gen[xcc].v;
+    br.l1_size = ld_agent(&gc->grp_size[xcc].v);
+    br.l2_arrive = &gc->arrive.v;
+    br.l2_gen = &gc->gen.v;
+    br.l2_size = ld_agent(&gc->ngroups);
+    br.member_release = false;
   } else {
-    tm.l1_arrive = &tm.ctl->arrive.v;
-    tm.l1_gen = &tm.ctl->gen.v;
-    tm.l1_size = tm.T;
-    tm.l2_arrive = nullptr;
-    tm.l2_gen = nullptr;
-    tm.l2_size = 0;
+    TeamCtl* oc = a.teams + own;
+    br.l1_arrive = &oc->arrive.v;
+    br.l1_gen = &oc->gen.v;
+    br.l1_size = a.G / a.nteams;
+    br.l2_arrive = nullptr;
+    br.l2_gen = nullptr;
+    br.l2_size = 0;
     // Teams inside one XCD share an L2 unless the placement is unexpected.
-    tm.member_release = (a.nteams % 8 != 0) || ld_agent(&gc->mismatch.v) != 0;
+    br.member_release = (a.nteams % 8 != 0) || ld_agent(&gc->mismatch.v) != 0;
   }
-  if (tid == 0) g_tm = tm;
-  __syncthreads();
   ph0 += lap();
 
   for (;;) {
     ull qi;
     if (a.serve) {
       // Serving: this team alone becomes idle and waits for its next
-      // assignment, then joins its group (leader's workspace, group ranks).
+      // assignment, then joins its group.
       if (grouped) {
-        tm.l2_arrive = nullptr;
-        tm.l2_gen = nullptr;
-        tm.l2_size = 0;
+        br.l2_arrive = nullptr;
+        br.l2_gen = nullptr;
+        br.l2_size = 0;
       }
       auto wait = [&]() {
-        if (tid == 0) serve_wait(a, gc, tm.own);
+        if (tid == 0) serve_wait(a, gc, own);
       };
-      if (!team_sync(a, sh, tm, wait)) return;
-      const TeamCtl* mine = a.teams + tm.own;
-      if (ld_agent(&mine->mb_exit)) break;
-      const ull leader = ld_agent(&mine->mb_leader);
-      tm.k = ld_agent(&mine->mb_k);
-      tm.T = tm.k * tm.Tteam;
-      tm.rank = ld_agent(&mine->mb_idx) * tm.Tteam + own_rank;
-      bind_workspace(a, tm, leader);
-      if (grouped && tm.k > 1) {
-        tm.l2_arrive = &tm.ctl->garrive.v;
-        tm.l2_gen = &tm.ctl->ggen.v;
-        tm.l2_size = tm.k;
-        tm.l2_base = ld_agent(&mine->mb_base);
-        tm.l2_epoch = 0;
+      if (!team_sync(a, sh, br, wait)) return;
+      const Join j = serve_join(a, grouped);
+      if (!j.ok) break;
+      if (j.l2_arrive) {
+        br.l2_arrive = j.l2_arrive;
+        br.l2_gen = j.l2_gen;
+        br.l2_size = j.l2_size;
+        br.l2_base = j.l2_base;
+        br.l2_epoch = 0;
       }
-      if (tid == 0) g_tm = tm;
-      __syncthreads();
       qi = ld_agent(&tm.ctl->query);
     } else {
       // Take the next source.
@@ -2089,46 +2190,18 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
         if (tid == 0)
           tm.ctl->query = (a.cancel && ld_agent(&gc->cancelled)) ? (ull)a.n_src : atom_add(&gc->next_query.v, 1ull);
       };
-      if (!team_sync(a, sh, tm, claim)) return;
+      if (!team_sync(a, sh, br, claim)) return;
       qi = ld_agent(&tm.ctl->query);
       if (qi >= (ull)a.n_src) break;
     }
     ull* out = a.dist_out + (a.serve ? ld_agent(&tm.ctl->out_row) : qi) * n;
-    dist = a.dist_int ? a.dist_int + tm.id * n : out;
+    ull* dist = a.dist_int ? a.dist_int + tm.id * n : out;
 
     // S0: delta = inf, Q empty; then delta[s] = 0 and Update(s).
-    for (ull i = tm.rank * WG + tid; i < n; i += tm.T * WG) dist[i] = INF;
-    if (tm.hint)
-      for (ull i = tm.rank * WG + tid; i < n; i += tm.T * WG) tm.hint[i] = HINT_NONE;
-    if (tm.lastkey)
-      for (ull i = tm.rank * WG + tid; i < n; i += tm.T * WG) tm.lastkey[i] = INF;
-    if (tm.ckey)
-      for (ull i = tm.rank * WG + tid; i < a.hcap; i += tm.T * WG) tm.ckey[i] = INF;
-    if (tm.key1) {
-      for (ull i = tm.rank * WG + tid; i < a.nwords; i += tm.T * WG) tm.key1[i] = INF;
-      for (ull i = tm.rank * WG + tid; i < a.n2; i += tm.T * WG) tm.key2[i] = INF;
-    }
-    for (ull i = tm.rank * WG + tid; i < a.nwords; i += tm.T * WG) tm.bitmap[i] = 0;
+    phase_init(a, dist);
     {
-      auto seed_source = [&]() {
-        if (tid < 48) reinterpret_cast<ull*>(&tm.ctl->slot[0])[tid] = 0ull;
-        tm.ctl->sel_hist[tid] = 0;
-        if (tid == 0) {
-          tm.ctl->sel_min = INF;
-          tm.ctl->sel_max = INF;
-          const int32_t src = a.serve ? (int32_t)tm.ctl->src : a.srcs[qi];
-          const int32_t s = a.inv ? a.inv[src] : src;
-          dist[s] = 0;
-          if (tm.hint) tm.hint[s] = 0;
-          if (tm.key1) {
-            tm.key1[s >> 6] = 0;
-            tm.key2[s >> 12] = 0;
-          }
-          tm.bitmap[s >> 6] = 1ull << (s & 63);
-          tm.L[0] = s;
-        }
-      };
-      if (!team_sync(a, sh, tm, seed_source)) return;
+      auto seed = [&]() { seed_source(a, dist, qi); };
+      if (!team_sync(a, sh, br, seed)) return;
       ph0 += lap();
     }
 
@@ -2182,7 +2255,7 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
           auto start = [&]() {
             if (tid == 0) select_serial(tm.ctl, true, 0, rho);
           };
-          if (!team_sync(a, sh, tm, start)) return;
+          if (!team_sync(a, sh, br, start)) return;
           int top = (int)ld_agent(&tm.ctl->sel_top);
           while (top > 0) {
             const int width = top < 8 ? top : 8;
@@ -2192,7 +2265,7 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
             auto pick = [&]() {
               if (tid == 0) select_serial(tm.ctl, false, shift, 0);
             };
-            if (!team_sync(a, sh, tm, pick)) return;
+            if (!team_sync(a, sh, br, pick)) return;
             top = shift;
           }
           theta = ld_agent(&tm.ctl->sel_prefix);
@@ -2220,26 +2293,27 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
             }
             if (tid == 0) tm.ctl->theta = th;
           };
-          if (!team_sync(a, sh, tm, choose)) return;
+          if (!team_sync(a, sh, br, choose)) return;
           ph1 += lap();
           theta = ld_agent(&tm.ctl->theta);
         }
       }
 
       // ---- S2: Extract(theta) over this workgroup's slice ----
-      const ExtractOut ex = tm.key1      ? phase_extract_tree(a, dist, S, theta)
+      const bool tree = tm.key1 != nullptr;
+      const ExtractOut ex = tree          ? phase_extract_tree(a, dist, S, theta)
                             : !dense       ? phase_extract_list(a, dist, S, Lcur, Lnext, q, theta, emit)
                             : emit        ? phase_extract_dense(a, dist, S, Lnext, theta, emit)
                             : q * 4 >= n  ? phase_extract_dense_words(a, dist, S, theta)
                                           : phase_extract_dense_fast(a, dist, S, theta);
-      if (!team_sync(a, sh, tm, NoSerial{})) return;
+      if (!team_sync(a, sh, br, NoSerial{})) return;
       ph2 += lap();
       const long long t_relax = wall_clock64();
 
       // ---- S3/S4: Relax + Update ----
       // Local expansion in super-sparse steps: list steps whose previous
       // step relaxed fewer than super_sparse arcs per vertex on average.
-      const bool sparse = tm.key1 ? q <= a.sparse_q : !dense;
+      const bool sparse = tree ? q <= a.sparse_q : !dense;
       const bool local = a.local_budget && sparse && prev_e < (ull)a.super_sparse * umin(prev_x, INF / 64);
       phase_relax(a, dist, S, Lnext, emit, ex, local, theta);
       const unsigned flags = (dense ? 1u : 0u) | (emit ? 2u : 0u) | (sampled ? 4u : 0u) | (exact ? 8u : 0u);
@@ -2250,7 +2324,7 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
           __hip_atomic_store(&gc->cancelled, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       };
-      if (!team_sync(a, sh, tm, bookkeeping)) return;
+      if (!team_sync(a, sh, br, bookkeeping)) return;
       ph3 += lap();
       if (a.cancel && (ld_agent(&tm.ctl->status) & ST_CANCELLED)) break;
 
@@ -2261,21 +2335,7 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
       prev_e = ld_agent(&S->edges);
       list_valid = emit && ld_agent(&S->list_next) <= a.lcap;
     }
-    // Distances back in the caller's vertex ids, and the row checksum.
-    ull h = 0;
-    if (a.dist_int) {
-      for (ull v = tm.rank * WG + tid; v < n; v += tm.T * WG) {
-        const ull d = ld_agent(&dist[a.inv[v]]);
-        out[v] = d;
-        if (a.hash) h += row_mix(v, d);
-      }
-    } else if (a.hash) {
-      for (ull v = tm.rank * WG + tid; v < n; v += tm.T * WG) h += row_mix(v, ld_agent(&out[v]));
-    }
-    if (a.hash) {
-      h = wave_sum(h);
-      if (lane_id() == 0) atom_add(&tm.ctl->hash_acc, h);
-    }
+    phase_copyout(a, dist, out);
     if (a.serve) {
       // The group's last barrier for this request publishes it; the row must
       // be visible outside the device (system scope) first.
@@ -2285,11 +2345,11 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
       auto publish = [&]() {
         if (tid == 0) serve_publish(a, tm.ctl);
       };
-      if (!team_sync(a, sh, tm, publish)) return;
+      if (!team_sync(a, sh, br, publish)) return;
     }
   }
   if (own_rank == 0 && tid == 0) {
-    TeamCtl* pc = a.teams + tm.own;
+    TeamCtl* pc = a.teams + own;
     pc->phase_ticks[0] += ph0;
     pc->phase_ticks[1] += ph1;
     pc->phase_ticks[2] += ph2;
