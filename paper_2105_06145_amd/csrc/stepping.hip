@@ -1438,13 +1438,11 @@ __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* 
 // with one key, u's current key read once (or its key at extraction with
 // snapshot keys); a chunk already pushed with that very key (ckey) is
 // skipped, since every WriteMin of it would fail.
-__device__ __noinline__ RelaxAcc relax_hub_chunks(const KArgs& a, ull* dist, StepSlot* S, int32_t* Lnext,
-                                                  bool emit, const Local lx) {
+__device__ __forceinline__ RelaxAcc relax_hub_chunks(const KArgs& a, ull* dist, StepSlot* S, int32_t* Lnext,
+                                                     bool emit, const Local lx) {
   const Team& tm = g_tm;
   Shared& sh = g_sh;
   const unsigned tid = threadIdx.x;
-  // Counts in registers (this function is not inlined: a reference to the
-  // caller's counters would put them in scratch memory).
   RelaxAcc acc{0, 0, 0, INF, 0, 0};
   const ArcSrc arcs{a.edges, a.tgt, a.wt};
   const ull nH = ld_agent(&S->h_count);
