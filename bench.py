@@ -11,7 +11,8 @@ the K timed solves use the fastest.
 
 The default line also carries the metric's other workloads, each under its
 own key: `road_delta_sweep` (the 5000 x 5000 road grid, Delta*-stepping with
-Delta = 2^10 .. 2^16 and Bellman-Ford: time, steps, time per step),
+Delta = 2^10 .. 2^16 and Bellman-Ford: time, steps, time per step; then
+Delta and the local-expansion budget together around the fastest),
 `knn_batched` (a 10-NN graph of 10^7 points, 64 queries in one launch
 against the same queries one launch each) and `latency` (a short serving
 run: R-MAT scale 22 and a 2000 x 2000 road grid resident, Poisson arrivals,
@@ -250,6 +251,19 @@ def measure_ceilings(torch, g, relax_arcs: int, relax_ms: float) -> dict:
                                                                        vp(sink.data_ptr()), st))
         out[f"atomic_min64_{name}"] = rate(lambda: L.sssp_ceiling_atomic_min64(vp(idx.data_ptr()), count,
                                                                                vp(t64.data_ptr()), st))
+    # Gathers that always hit L2: the index stream walks the table slice by
+    # slice (2^18 entries = 512 KB per slice, uniform within it), so every
+    # XCD's L2 holds the slice being read. What binning the arcs by target
+    # range (to make the key-bound reads L2-resident) could at best reach.
+    slice_entries = 1 << 18
+    nsl = max(1, n // slice_entries)
+    per = count // nsl
+    idx_l2 = ((torch.arange(count, device="cuda", dtype=torch.int64) // per).clamp(max=nsl - 1) * slice_entries
+              + torch.randint(0, min(n, slice_entries), (count,), device="cuda")).to(torch.int32)
+    out["gather16_l2_slices"] = rate(lambda: L.sssp_ceiling_gather16(vp(idx_l2.data_ptr()), count, vp(t16.data_ptr()),
+                                                                     vp(sink.data_ptr()), st))
+    out["l2_slice_entries"] = slice_entries
+    del idx_l2
     out["relax_arcs_per_s"] = round(relax_arcs / (relax_ms * 1e-3) / 1e9, 2)
     out["relax_frac_of_gather16_arc_targets"] = round(out["relax_arcs_per_s"] / out["gather16_arc_targets"], 3)
     del idx_deg, idx_uni, t16, t64, sink
@@ -376,7 +390,9 @@ def run_single(args, torch, sp, w):
 def run_road_sweep(args, torch, sp):
     """Delta*-stepping over Delta = 2^10 .. 2^16 and Bellman-Ford on the road
     workload, one solve each from its seeded source: time, steps, time per
-    step (the paper's Delta and BF rows; Sec. 6 on road graphs)."""
+    step (the paper's Delta and BF rows; Sec. 6 on road graphs). Then the
+    autotuner's joint candidates of Delta and local-expansion budget around
+    the fastest Delta."""
     import graphgen
     w = graphgen.workload("road5000", sources=1)
     g = w.graph
@@ -396,11 +412,25 @@ def run_road_sweep(args, torch, sp):
                      "gteps_useful": round(m_reach / (ms * 1e6), 4),
                      "local_vertices": int(st["local_vertices"])})
         log(f"  road5000 {kw}: {ms:.2f} ms, {st['steps']} steps")
+    best = min((r for r in rows if r["rule"] == "delta"), key=lambda r: r["ms"])
+    # Delta and the local-expansion budget together (the autotuner's joint
+    # step), around the fastest Delta at the default budget.
+    from paper_2105_06145_amd import autotune as at
+    joint = []
+    for d, budget in at.local_candidates(best["delta"]):
+        _, st = sp.solve(G, [src], rule="delta", delta=d, tuning={"local_budget": budget}, out=out)
+        ms = st["device_ms"]
+        joint.append({"delta": d, "local_budget": budget, "ms": round(ms, 3), "steps": int(st["steps"]),
+                      "edges_relaxed": int(st["edges_relaxed"]), "local_vertices": int(st["local_vertices"]),
+                      "gteps_useful": round(m_reach / (ms * 1e6), 4)})
+        log(f"  road5000 delta {d}, local budget {budget}: {ms:.2f} ms, {st['steps']} steps")
     G.close()
     torch.cuda.synchronize()
-    best = min((r for r in rows if r["rule"] == "delta"), key=lambda r: r["ms"])
+    jbest = min(joint, key=lambda r: r["ms"])
     return {"workload": WORKLOADS["road5000"], "n": g.n, "m": g.m, "source": src, "useful_arcs": m_reach,
-            "per_rule": rows, "fastest_delta": best["delta"]}
+            "per_rule": rows, "fastest_delta": best["delta"],
+            "delta_and_local_budget": {"per_pair": joint, "default_budget": at.DEFAULT_LOCAL_BUDGET,
+                                       "fastest": {k: jbest[k] for k in ("delta", "local_budget", "ms")}}}
 
 
 def run_knn_compare(args, torch, sp):

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define SSSP_ABI_VERSION 3
+#define SSSP_ABI_VERSION 4
 
 typedef enum {
   SSSP_OK = 0,
@@ -169,6 +169,18 @@ typedef struct {
                              0 = library default (on for launches of one team on graphs whose
                              average out-degree is at least super_sparse_degree), 1 = on,
                              0xFFFFFFFF = off */
+  uint32_t hub_defer_degree; /* SSSP_RULE_RHO, sampled steps: a queued vertex of out-degree at
+                             least this (rounded down to a power of two) is extracted only when
+                             its key is at most theta_h, the (rho / hub_defer_div)-th smallest
+                             key of the same sample, not theta. A high-degree vertex's key keeps
+                             falling while the frontier passes its many neighbours, so relaxing
+                             it at once means relaxing it again after each fall. Every other
+                             vertex at or below theta is still extracted and the smallest key is
+                             always at or below theta_h, so the distances do not change; steps
+                             and arcs relaxed do. Needs the degree numbering (ignored under
+                             SSSP_KEEP_ORDER and SSSP_BORROW_DEVICE). 0 = library default
+                             (off), 0xFFFFFFFF = off */
+  uint32_t hub_defer_div;   /* theta_h's rank divisor for hub_defer_degree (0 = default 10) */
 } sssp_tuning;
 
 /* One record per step, written when params.trace is set. */

@@ -14,7 +14,13 @@ This module searches them by timing real solves on the device:
      rho over powers of four from n down to 2^8, Delta over the median arc
      weight times powers of four; then the neighbouring powers of two;
   2. for batches, the number of teams the persistent grid is split into;
-  3. the hub-degree threshold, the size of the arc chunks hubs are cut into
+  3. on graphs that relax locally (average out-degree below the library's
+     super-sparse threshold, Sec. 6 on large neighbour sets), the rule
+     parameter and the local-expansion budget together: a larger Delta (or
+     rho) puts more hops into one step, and with the default budget the
+     expansion then stops short of them and the steps multiply, so values
+     up to four times the best are tried with budgets grown alike;
+  4. the hub-degree threshold, the size of the arc chunks hubs are cut into
      (the tile shape of their relaxation), the explicit-list switch, then
      the queue structure (flat array or tournament tree, Sec. 4).
 
@@ -52,6 +58,26 @@ def delta_candidates(w_median: int) -> list[int]:
     return [max(1, base << k) if k >= 0 else max(1, base >> -k) for k in range(10, -3, -2)]
 
 
+# The library's defaults for local expansion (sssp_tuning.local_budget and
+# super_sparse_degree).
+DEFAULT_LOCAL_BUDGET = 4096
+SUPER_SPARSE_DEGREE = 10
+
+
+def local_candidates(v0: int) -> list[tuple[int, int]]:
+    """(rule parameter, local budget) pairs tried around the best parameter
+    v0 found with the default budget: v0 with twice the budget, 2 * v0 with
+    2 and 4 times it, 4 * v0 with 4 and 8 times it."""
+    b = DEFAULT_LOCAL_BUDGET
+    return [(v0, 2 * b), (2 * v0, 2 * b), (2 * v0, 4 * b), (4 * v0, 4 * b), (4 * v0, 8 * b)]
+
+
+def relaxes_locally(n: int, m: int) -> bool:
+    """Whether the library runs local expansion on a graph of this size
+    (average out-degree below the super-sparse threshold)."""
+    return n > 0 and m < SUPER_SPARSE_DEGREE * n
+
+
 def team_candidates(nsrc: int, grid: int = 1024) -> list[int]:
     out, t = [], 8
     while t <= grid and t < 2 * max(nsrc, 8):
@@ -61,8 +87,8 @@ def team_candidates(nsrc: int, grid: int = 1024) -> list[int]:
 
 
 class Tuner:
-    """Coordinate search over (rule parameter, teams, hub_degree, chunk_edges,
-    list_divisor).
+    """Coordinate search over (rule parameter, teams, local_budget,
+    hub_degree, chunk_edges, list_divisor, queue).
 
     `measure(config) -> ms` times one configuration; by default it runs the
     solver on the given graph and sources. A config is a dict with keys rule,
@@ -111,7 +137,8 @@ class Tuner:
             best[0], best[1] = cfg, ms
         return ms
 
-    def search(self, n: int, nsrc: int, w_median: int, rules=("rho", "delta"), grid: int = 1024) -> dict:
+    def search(self, n: int, nsrc: int, w_median: int, rules=("rho", "delta"), grid: int = 1024,
+               local: bool = False) -> dict:
         t0 = time.monotonic()
         best = [None, math.inf]
 
@@ -146,7 +173,14 @@ class Tuner:
             for v in (v0 // 2, v0 * 2):
                 if v >= 1 and v not in scores and not out_of_time():
                     scores[v] = self._eval({"rule": rule, name: v, "tuning": dict(base_tuning)}, best)
-        # 2.-3. kernel knobs, one at a time around the best so far.
+        # 3. rule parameter and local-expansion budget together.
+        if local and best[0] is not None and best[0]["rule"] in ("rho", "delta"):
+            name = best[0]["rule"]
+            for v, budget in local_candidates(best[0][name]):
+                if out_of_time():
+                    break
+                self._eval({"rule": name, name: v, "tuning": {**base_tuning, "local_budget": budget}}, best)
+        # 2., 4. kernel knobs, one at a time around the best so far.
         knobs = []
         if nsrc > 1:
             knobs.append(("teams", team_candidates(nsrc, grid)))
@@ -189,7 +223,7 @@ class Tuner:
                 return times[len(times) // 2]
             self._measure = measure
         w_median = graph.summary.get("weight_q10_50_90", [0, 1, 0])[1] or 1
-        cfg = self.search(graph.n, nsrc, w_median, rules)
+        cfg = self.search(graph.n, nsrc, w_median, rules, local=relaxes_locally(graph.n, getattr(graph, "m", 0)))
         self._store(self.key(fp, nsrc), cfg)
         return cfg
 

@@ -124,6 +124,25 @@ __global__ void relabel_rows_kernel(const int32_t* perm, const int32_t* inv, con
   }
 }
 
+// count[k] = the number of vertices of out-degree at least 2^k (k = 0 .. 32),
+// on offsets whose degrees do not increase with the id: the first id whose
+// degree is below 2^k, by binary search. One thread per k.
+__global__ void degree_ranks_kernel(const int64_t* off, ull n, ull* count) {
+  const unsigned k = threadIdx.x;
+  if (k > 32) return;
+  const ull need = 1ull << k;
+  ull lo = 0, hi = n;
+  while (lo < hi) {
+    const ull mid = lo + (hi - lo) / 2;
+    if ((ull)(off[mid + 1] - off[mid]) >= need) {
+      lo = mid + 1;
+    } else {
+      hi = mid;
+    }
+  }
+  count[k] = lo;
+}
+
 // Swap the 32-bit halves of each packed arc: (weight << 32) | target <->
 // (target << 32) | weight, so that a sort on the upper half orders a row by
 // target.
@@ -137,9 +156,9 @@ __global__ void swap_halves_kernel(ull* e, ull m) {
 // Renumber g's vertices by decreasing degree (see the file comment).
 sssp_status relabel_by_degree(sssp_graph* g, hipStream_t st) {
   const ull n = (ull)g->n, m = (ull)g->m;
-  DevBuf keys, keys2, ids, newdeg, newoff, newedges, sorted, tmp;
+  DevBuf keys, keys2, ids, newdeg, newoff, newedges, sorted, tmp, ranks;
   auto cleanup = [&]() {
-    for (DevBuf* b : {&keys, &keys2, &ids, &newdeg, &newoff, &newedges, &sorted, &tmp}) b->release(st);
+    for (DevBuf* b : {&keys, &keys2, &ids, &newdeg, &newoff, &newedges, &sorted, &tmp, &ranks}) b->release(st);
   };
   hipError_t e;
   do {
@@ -197,6 +216,10 @@ sssp_status relabel_by_degree(sssp_graph* g, hipStream_t st) {
       if ((e = hipGetLastError()) != hipSuccess) break;
       std::swap(newedges, sorted);
     }
+    if ((e = ranks.alloc(33 * 8, st)) != hipSuccess) break;
+    degree_ranks_kernel<<<1, 64, 0, st>>>((const int64_t*)newoff.p, n, (ull*)ranks.p);
+    if ((e = hipGetLastError()) != hipSuccess) break;
+    if ((e = hipMemcpyAsync(g->deg_ge, ranks.p, 33 * 8, hipMemcpyDeviceToHost, st)) != hipSuccess) break;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) break;
     std::swap(g->off, newoff);
     std::swap(g->edges, newedges);

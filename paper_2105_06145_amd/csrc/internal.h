@@ -68,6 +68,9 @@ struct sssp_graph {
   sssp_impl::DevBuf edges;  // uint64[m]: (weight << 32) | internal target
   sssp_impl::DevBuf perm, inv;
   bool relabelled = false;
+  // Relabelled graphs (degrees do not increase with the id): deg_ge[k] is the
+  // number of vertices of out-degree at least 2^k, the ids 0 .. deg_ge[k] - 1.
+  uint64_t deg_ge[33] = {};
   // SSSP_BORROW_DEVICE: the caller's device targets and weights are used in
   // place (edges is then empty; the caller keeps them alive and unchanged
   // in shape until the graph is destroyed).

@@ -119,6 +119,7 @@ struct TeamCtl {
   Line arrive;  // team barrier (teams inside one XCD)
   Line gen;
   alignas(128) ull theta;
+  ull theta_h;  // deferred hubs' threshold of the step (rho rule with hub deferral)
   ull query;   // index of the source being solved
   ull status;  // 1: step limit reached on some query
   ull st_steps, st_extracted, st_edges, st_success, st_dense, st_sampled;
@@ -204,6 +205,9 @@ struct KArgs {
   ull* ckey;            // per team, hcap: the same per hub chunk (NULL: off)
   const uint32_t* cbase;  // hub u < nhub: index of u's first chunk in ckey (hubs are numbered first)
   uint64_t nhub;
+  uint64_t ndefer;      // sampled rho steps: vertices below this id (the highest degrees, numbered
+                        // first) are extracted only at keys <= theta_h (0: no deferral)
+  uint64_t defer_div;   // theta_h is the sampled (rho / defer_div)-th smallest key
   ull* key1;            // tournament-tree queue (NULL: flat array): per team, nwords (one node per bitmap word)
   ull* key2;            // per team, n2 (one node per 64 words)
   uint64_t n2;
@@ -783,6 +787,15 @@ __device__ __noinline__ void phase_sample(const KArgs& a, const ull* dist, StepS
   }
 }
 
+// Extract's thresholds: theta, and theta_h <= theta for the deferred hubs
+// (vertex ids below ndefer); ndefer = 0 when no vertex is deferred.
+struct Thresh {
+  ull theta, theta_h, ndefer;
+};
+__device__ __forceinline__ ull limit_of(const Thresh& th, int32_t v) {
+  return (ull)(uint32_t)v < th.ndefer ? th.theta_h : th.theta;
+}
+
 struct ExtractOut {
   uint32_t fcnt;  // entries written to this workgroup's F segment
   ull x;          // vertices extracted
@@ -795,13 +808,13 @@ struct ExtractOut {
 // the first segcap of each segment and leaves the others for the next step).
 template <int K>
 __device__ __forceinline__ void extract_round(const KArgs& a, const Team& tm, StepSlot* S, int32_t* Lnext,
-                                              ull theta, bool emit, bool atomic_clear, const int32_t (&v)[K],
+                                              const Thresh th, bool emit, bool atomic_clear, const int32_t (&v)[K],
                                               const ull (&d)[K], unsigned hubs, ExtractOut& o, ull& clear) {
   Shared& sh = g_sh;
   uint32_t ncand = 0;
 #pragma unroll
   for (int k = 0; k < K; ++k)
-    if (v[k] >= 0 && d[k] <= theta && !((hubs >> k) & 1u)) ++ncand;
+    if (v[k] >= 0 && d[k] <= limit_of(th, v[k]) && !((hubs >> k) & 1u)) ++ncand;
   uint32_t total;
   const uint32_t first = o.fcnt + wg_scan(sh, ncand, total);
   const ull room = a.segcap - o.fcnt;
@@ -813,7 +826,7 @@ __device__ __forceinline__ void extract_round(const KArgs& a, const Team& tm, St
     ev[k] = -1;
     if (v[k] < 0) continue;
     const ull bit = 1ull << (v[k] & 63);
-    bool ext = d[k] <= theta;
+    bool ext = d[k] <= limit_of(th, v[k]);
     if (ext && !((hubs >> k) & 1u)) {
       if (slot < a.segcap) {
         tm.Fb[slot] = v[k];
@@ -856,7 +869,7 @@ __device__ __forceinline__ void extract_round(const KArgs& a, const Team& tm, St
 // numbered first are spread over all workgroups). Each lane owns one word;
 // its members are read in rounds of BATCH keys.
 __device__ __noinline__ ExtractOut phase_extract_dense(const KArgs& a, const ull* dist, StepSlot* S,
-                                                       int32_t* Lnext, ull theta, bool emit) {
+                                                       int32_t* Lnext, const Thresh th, bool emit) {
   const Team& tm = g_tm;
   const ull nw = a.nwords, T = tm.T;
   const ull nblocks = (nw + BLOCK_WORDS - 1) / BLOCK_WORDS;
@@ -884,7 +897,7 @@ __device__ __noinline__ ExtractOut phase_extract_dense(const KArgs& a, const ull
       }
 #pragma unroll
       for (int k = 0; k < BATCH; ++k) d[k] = v[k] >= 0 ? ld_agent(&dist[v[k]]) : INF;
-      extract_round(a, tm, S, Lnext, theta, emit, false, v, d, hubs, o, clear);
+      extract_round(a, tm, S, Lnext, th, emit, false, v, d, hubs, o, clear);
     }
     if (clear) tm.bitmap[wi] = word & ~clear;  // this lane owns word wi
   }
@@ -918,7 +931,7 @@ __device__ __forceinline__ int select_bit(ull w, uint32_t n) {
 // the word's owner; F slots come from an LDS counter, hubs are recorded with
 // one atomic per wave.
 __device__ __noinline__ ExtractOut phase_extract_dense_fast(const KArgs& a, const ull* dist, StepSlot* S,
-                                                            ull theta) {
+                                                            const Thresh th) {
   const Team& tm = g_tm;
   Shared& sh = g_sh;
   const unsigned tid = threadIdx.x;
@@ -989,7 +1002,7 @@ __device__ __noinline__ ExtractOut phase_extract_dense_fast(const KArgs& a, cons
       for (int k = 0; k < BATCH; ++k) {
         if (v[k] < 0) continue;
         const ull bit = 1ull << (v[k] & 63);
-        bool ext = d[k] <= theta;
+        bool ext = d[k] <= limit_of(th, v[k]);
         if (ext) {
           if ((whub[own[k]] & bit) != 0) {
             hub_taken |= 1u << k;
@@ -1035,7 +1048,7 @@ __device__ __noinline__ ExtractOut phase_extract_dense_fast(const KArgs& a, cons
 constexpr int WPI = 4;
 
 __device__ __noinline__ ExtractOut phase_extract_dense_words(const KArgs& a, const ull* dist, StepSlot* S,
-                                                             ull theta) {
+                                                             const Thresh th) {
   const Team& tm = g_tm;
   Shared& sh = g_sh;
   const ull nw = a.nwords, T = tm.T;
@@ -1080,7 +1093,7 @@ __device__ __noinline__ ExtractOut phase_extract_dense_words(const KArgs& a, con
       const int32_t v = (int32_t)(wi[k] * 64 + lane);
       const bool member = (word[k] >> lane) & 1ull;
       const bool hub = (hubw[k] >> lane) & 1ull;
-      bool ext = member && d[k] <= theta;
+      bool ext = member && d[k] <= limit_of(th, v);
       const ull want = __ballot(ext && !hub);
       if (want) {
         uint32_t base = 0;
@@ -1121,7 +1134,8 @@ __device__ __noinline__ ExtractOut phase_extract_dense_words(const KArgs& a, con
 // (the smallest key left in it). The node's key is then recomputed from its
 // 64 children. The keys of skipped nodes and of members left bound the keys
 // kept in Q.
-__device__ __noinline__ ExtractOut phase_extract_tree(const KArgs& a, const ull* dist, StepSlot* S, ull theta) {
+__device__ __noinline__ ExtractOut phase_extract_tree(const KArgs& a, const ull* dist, StepSlot* S, const Thresh th) {
+  const ull theta = th.theta;  // node keys are compared with the larger threshold
   const Team& tm = g_tm;
   Shared& sh = g_sh;
   const ull nw = a.nwords;
@@ -1159,7 +1173,7 @@ __device__ __noinline__ ExtractOut phase_extract_tree(const KArgs& a, const ull*
         const bool member = (word[k] >> lane) & 1ull;
         const int32_t v = (int32_t)(wi[k] * 64 + lane);
         const bool hub = member && ((ld_plain(&a.hubmask[wi[k]]) >> lane) & 1ull);
-        bool ext = member && d[k] <= theta;
+        bool ext = member && d[k] <= limit_of(th, v);
         const ull want = __ballot(ext && !hub);
         if (want) {
           uint32_t base = 0;
@@ -1204,7 +1218,7 @@ __device__ __noinline__ ExtractOut phase_extract_tree(const KArgs& a, const ull*
 
 // S2, list step: this workgroup's contiguous slice of the explicit list.
 __device__ __noinline__ ExtractOut phase_extract_list(const KArgs& a, const ull* dist, StepSlot* S,
-                                                      const int32_t* Lcur, int32_t* Lnext, ull q, ull theta,
+                                                      const int32_t* Lcur, int32_t* Lnext, ull q, const Thresh th,
                                                       bool emit) {
   const Team& tm = g_tm;
   const ull lo = tm.rank * q / tm.T, hi = (tm.rank + 1) * q / tm.T;
@@ -1227,7 +1241,7 @@ __device__ __noinline__ ExtractOut phase_extract_list(const KArgs& a, const ull*
         if ((ld_plain(&a.hubmask[v[k] >> 6]) >> (v[k] & 63)) & 1ull) hubs |= 1u << k;
       }
     }
-    extract_round(a, tm, S, Lnext, theta, emit, true, v, d, hubs, o, unused);
+    extract_round(a, tm, S, Lnext, th, emit, true, v, d, hubs, o, unused);
   }
   return o;
 }
@@ -1303,7 +1317,8 @@ __device__ __forceinline__ void relax_batch(const KArgs& a, const Team& tm, ull*
     // relaxed by the team (local expansion is for small neighbour sets; a
     // high-degree vertex in one workgroup's list would serialise its arcs
     // there).
-    if (lx.on && nd[k] <= lx.theta && !((ld_plain(&a.bigmask[fv[k] >> 6]) >> (fv[k] & 63)) & 1ull)) {
+    if (lx.on && nd[k] <= lx.theta && (ull)(uint32_t)fv[k] >= a.ndefer &&
+        !((ld_plain(&a.bigmask[fv[k] >> 6]) >> (fv[k] & 63)) & 1ull)) {
       const uint32_t slot = atomicAdd(&sh.lqn[lx.nxt], 1u);
       if (slot < (uint32_t)LQ) {
         sh.lq[lx.nxt][slot] = fv[k];
@@ -2233,6 +2248,7 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
 
       // ---- S1: ExtDist ----
       ull theta = INF;
+      ull theta_h = INF;  // set in sampled rho steps with hub deferral; else theta
       bool sampled = false, exact = false;
       if (a.rule == SSSP_RULE_BF) {
         theta = INF;
@@ -2282,28 +2298,41 @@ __global__ __launch_bounds__(WG, 4) void stepping_kernel(const KArgs* __restrict
           phase_sample(a, dist, S, Lcur, q, dense, probes, splitmix(a.seed ^ qi, t));
           auto choose = [&]() {
             const ull s = ld_agent(&S->nsamples);
-            ull th = INF;
+            ull th = INF, th_h = INF;
             if (s > 0) {
               ull k = (rho_eff * s + q - 1) / q;  // ceil(rho * s / q)
               if (k < 1) k = 1;
               if (k > s) k = s;
               th = wg_select_kth(tm.samples, s, k);
+              th_h = th;
+              if (a.ndefer) {
+                // Hub deferral: the (rho / defer_div)-th smallest key of the same sample.
+                const ull rho_h = rho_eff / a.defer_div > 0 ? rho_eff / a.defer_div : 1;
+                ull kh = (rho_h * s + q - 1) / q;
+                if (kh < 1) kh = 1;
+                if (kh < k) th_h = wg_select_kth(tm.samples, s, kh);
+              }
             }
-            if (tid == 0) tm.ctl->theta = th;
+            if (tid == 0) {
+              tm.ctl->theta = th;
+              tm.ctl->theta_h = th_h;
+            }
           };
           if (!team_sync(a, sh, br, choose)) return;
           ph1 += lap();
           theta = ld_agent(&tm.ctl->theta);
+          theta_h = ld_agent(&tm.ctl->theta_h);
         }
       }
 
       // ---- S2: Extract(theta) over this workgroup's slice ----
       const bool tree = tm.key1 != nullptr;
-      const ExtractOut ex = tree          ? phase_extract_tree(a, dist, S, theta)
-                            : !dense       ? phase_extract_list(a, dist, S, Lcur, Lnext, q, theta, emit)
-                            : emit        ? phase_extract_dense(a, dist, S, Lnext, theta, emit)
-                            : q * 4 >= n  ? phase_extract_dense_words(a, dist, S, theta)
-                                          : phase_extract_dense_fast(a, dist, S, theta);
+      const Thresh th{theta, sampled ? umin(theta_h, theta) : theta, sampled ? a.ndefer : 0};
+      const ExtractOut ex = tree          ? phase_extract_tree(a, dist, S, th)
+                            : !dense       ? phase_extract_list(a, dist, S, Lcur, Lnext, q, th, emit)
+                            : emit        ? phase_extract_dense(a, dist, S, Lnext, th, emit)
+                            : q * 4 >= n  ? phase_extract_dense_words(a, dist, S, th)
+                                          : phase_extract_dense_fast(a, dist, S, th);
       if (!team_sync(a, sh, br, NoSerial{})) return;
       ph2 += lap();
       const long long t_relax = wall_clock64();
@@ -2725,6 +2754,11 @@ void fill_args(const sssp_graph* g, Launch& L, const WsView& w, uint64_t* dist) 
   if ((uint64_t)g->m >= (uint64_t)tu.super_sparse_degree * (uint64_t)g->n) a.local_budget = 0;
   // Bidirectional relaxation reads current keys too; it needs symmetric arcs.
   a.pull = (!a.snapshot && g->undirected && tu.pull != 0xFFFFFFFFu && tu.pull != 0) ? 1u : 0u;
+  // Hub deferral (rho rule): on a graph numbered by degree the vertices of
+  // out-degree at least 2^k are the ids below deg_ge[k].
+  a.defer_div = tu.hub_defer_div ? tu.hub_defer_div : 10u;
+  if (p.rule == SSSP_RULE_RHO && g->relabelled && tu.hub_defer_degree != 0 && tu.hub_defer_degree != 0xFFFFFFFFu)
+    a.ndefer = g->deg_ge[31 - __builtin_clz(tu.hub_defer_degree)];
 }
 
 // Plan the launch, make sure the graph's workspace fits it, and fill the

@@ -58,7 +58,7 @@ def test_struct_layouts_match_header(tmp_path):
 
 
 def test_version_strings_defaults():
-    assert N.sssp_abi_version() == 3
+    assert N.sssp_abi_version() == 4
     assert N.sssp_status_string(N.SSSP_OK) == "ok"
     assert "argument" in N.sssp_status_string(N.SSSP_ERR_INVALID_ARGUMENT)
     assert N.sssp_status_string(99) == "unknown status"

@@ -83,6 +83,38 @@ def test_search_single_source_has_no_teams_and_obeys_budget():
     assert len(tu0.history) == 1 and cfg0["ms"] == tu0.history[0][1]
 
 
+def local_model(cfg):
+    """Delta*-stepping on a graph that relaxes locally: Delta = 2^lg needs a
+    local budget of 4096 * 2^(lg - 12); below it the steps multiply (cost
+    100). With enough budget, larger Delta is cheaper (fewer steps)."""
+    if cfg["rule"] != "delta":
+        return 1000.0
+    lg = math.log2(cfg["delta"])
+    lb = cfg.get("tuning", {}).get("local_budget", at.DEFAULT_LOCAL_BUDGET)
+    need = at.DEFAULT_LOCAL_BUDGET * 2 ** max(0.0, lg - 12)
+    if lg < 12:
+        return 12 + (12 - lg) ** 2
+    if lb < need:
+        return 100.0
+    return 12 - 0.3 * (lg - 12) + 0.1 * math.log2(lb / need)
+
+
+def test_local_budget_searched_with_delta():
+    assert at.local_candidates(1 << 12) == [(1 << 12, 8192), (1 << 13, 8192), (1 << 13, 16384),
+                                            (1 << 14, 16384), (1 << 14, 32768)]
+    assert at.relaxes_locally(1000, 3600) and not at.relaxes_locally(1000, 10000)
+    tu = at.Tuner(measure=local_model)
+    cfg = tu.search(n=1 << 20, nsrc=1, w_median=1 << 12, rules=("delta",), local=True)
+    # The default budget finds Delta = 2^12; the joint step finds 2^14 with 4x the budget.
+    assert cfg["delta"] == 1 << 14 and cfg["tuning"]["local_budget"] == 16384
+    assert cfg["ms"] == pytest.approx(11.4)
+    # Without local expansion the budget is never tried.
+    tu2 = at.Tuner(measure=local_model)
+    cfg2 = tu2.search(n=1 << 20, nsrc=1, w_median=1 << 12, rules=("delta",))
+    assert cfg2["delta"] == 1 << 12
+    assert all("local_budget" not in c.get("tuning", {}) for c, _ in tu2.history)
+
+
 def test_cache_round_trip(tmp_path):
     path = str(tmp_path / "tune.json")
     tu = at.Tuner(cache_path=path, measure=cost_model)

@@ -606,6 +606,11 @@ def test_full_rmat24_rho_sweep(sp, rmat24):
     dist, st = sp.solve(G, [s], rule="rho", rho=1 << 16, tuning={"queue": 1})
     assert_same(sp.to_numpy_u64(dist)[0], exp, "rmat24 tournament tree rho=2^16")
     print(f"rmat24 tree rho=65536 steps={st['steps']} ms={st['device_ms']:.2f}", flush=True)
+    # hub deferral at the benchmark's deferral setting
+    dist, st = sp.solve(G, [s], rule="rho", rho=1 << 21, tuning={"hub_defer_degree": 32, "hub_defer_div": 1000})
+    assert_same(sp.to_numpy_u64(dist)[0], exp, "rmat24 hub deferral rho=2^21")
+    print(f"rmat24 deferral rho=2^21 steps={st['steps']} edges={st['edges_relaxed']} ms={st['device_ms']:.2f}",
+          flush=True)
     pending = sp.solve_async(G, [s], rule="rho", rho=1 << 18)
     dist, _ = pending.wait()
     assert_same(sp.to_numpy_u64(dist)[0], exp, "rmat24 asynchronous solve")
@@ -677,6 +682,55 @@ def test_repeat_skip_keeps_distances(sp, teams):
                 assert st_off["repeat_skipped"] == 0
                 skipped_any += st_on["repeat_skipped"]
         assert skipped_any > 0
+    finally:
+        G.close()
+
+
+@pytest.mark.parametrize("teams", [1, 8])
+def test_hub_deferral_keeps_distances(sp, teams):
+    """Hub deferral (high-degree vertices extracted only at keys <= theta_h in
+    sampled rho steps) leaves every distance as the oracle's, with the tree
+    queue, snapshot keys and tiny hub chunks too, and on a power-law graph
+    relaxes fewer arcs."""
+    g = graphgen.rmat(14, 16, seed=81)
+    srcs = [3, 4000, 11111]
+    exp = [ref(g, s) for s in srcs]
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+    try:
+        arcs = {}
+        for rho in (16, 2048, 1 << 20):
+            for tun in ({}, {"hub_defer_degree": 16, "hub_defer_div": 1000}, {"hub_defer_degree": 64},
+                        {"hub_defer_degree": 1, "hub_defer_div": 4},
+                        {"hub_defer_degree": 16, "hub_defer_div": 1000, "queue": 1},
+                        {"hub_defer_degree": 2, "hub_defer_div": 0xFFFFFFFF, "hub_degree": 64, "chunk_edges": 64}):
+                tv = {**tun, "teams": teams}
+                for snap in (False, True):
+                    d, st = sp.solve(G, srcs, rule="rho", rho=rho, tuning=tv, snapshot_keys=snap)
+                    got = sp.to_numpy_u64(d)
+                    for i in range(len(srcs)):
+                        assert_same(got[i], exp[i], f"rho {rho} {tv} snapshot {snap} source {srcs[i]}")
+                    if rho == 2048 and not snap and "queue" not in tun:
+                        arcs[(tun.get("hub_defer_degree"), tun.get("hub_defer_div"))] = st["edges_relaxed"]
+        assert arcs[(16, 1000)] < arcs[(None, None)], arcs
+    finally:
+        G.close()
+    # Ignored on graphs kept in the caller's order; with local expansion on a
+    # road-like graph (low-degree hubs deferred) the distances stay.
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights, reorder=False)
+    try:
+        d, _ = sp.solve(G, srcs, rule="rho", rho=2048, tuning={"hub_defer_degree": 16, "teams": teams})
+        for i in range(len(srcs)):
+            assert_same(sp.to_numpy_u64(d)[i], exp[i], f"keep order source {srcs[i]}")
+    finally:
+        G.close()
+    r = graphgen.road(60, 60, seed=5)
+    rs = [0, 1234]
+    G = sp.Graph.from_csr(r.offsets, r.targets, r.weights)
+    try:
+        for tun in ({"hub_defer_degree": 4, "hub_defer_div": 100}, {"hub_defer_degree": 1, "hub_defer_div": 3}):
+            d, st = sp.solve(G, rs, rule="rho", rho=64, tuning={**tun, "teams": teams})
+            for i, s in enumerate(rs):
+                assert_same(sp.to_numpy_u64(d)[i], ref(r, s), f"road {tun} source {s}")
     finally:
         G.close()
 
