@@ -6,8 +6,11 @@ empty). The default workload is the power-law graph: R-MAT scale 24, edge
 factor 16 (a = 0.57, b = 0.19, c = 0.19), symmetrised and deduplicated,
 weights uniform in [1, 2^18), ten seeded sources in the largest component,
 rho-stepping. The graph is resident in HBM before timing starts. rho is
-swept over 2^16 .. 2^22 first (one solve per source each; `rho_sweep`) and
-the K timed solves use the fastest.
+swept over 2^16 .. 2^22 first with the paper's rule (one solve per source
+each; `rho_sweep`, fastest in `paper_rule`), then with hub deferral at the
+autotuner's settings around the fastest rho (`hub_defer_sweep`: vertices of
+high out-degree extracted only at keys up to a much smaller sampled rank);
+the K timed solves use the fastest configuration of both.
 
 The default line also carries the metric's other workloads, each under its
 own key: `road_delta_sweep` (the 5000 x 5000 road grid, Delta*-stepping with
@@ -108,16 +111,25 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str, rho: int):
+def traffic_key(rho: int, tuning) -> str:
+    """Key of a configuration in the traffic file: rho, plus the hub-deferral
+    setting when there is one ("2097152:defer32/1000")."""
+    if tuning and tuning.get("hub_defer_degree"):
+        return f"{rho}:defer{tuning['hub_defer_degree']}/{tuning['hub_defer_div']}"
+    return str(rho)
+
+
+def load_traffic(workload: str, key: str):
     """HBM bytes per launch from the committed rocprofv3 counters, or None when
-    they were taken on other kernel sources, another workload or another rho."""
+    they were taken on other kernel sources, another workload or another
+    configuration (traffic_key)."""
     try:
         d = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     if d.get("kernel_sha") != kernel_sha() or d.get("workload") != workload:
         return None
-    rec = d.get("by_rho", {}).get(str(rho))
+    rec = d.get("by_rho", {}).get(key)
     return rec.get("traffic_bytes_per_launch") if rec else None
 
 
@@ -280,8 +292,34 @@ def run_single(args, torch, sp, w):
     out = torch.empty((1, g.n), dtype=torch.int64, device="cuda")
 
     rule = "rho" if args.workload != "road5000" else "delta"
-    sweep = []
+    sweep, defer_sweep = [], []
     m_reach_of = {}
+    tuning = None  # tuning of the timed solves (hub deferral), or None
+
+    def sweep_point(rho, tun):
+        """One solve per source (the timed solves' sources), averaged."""
+        times, balg, edges_r, steps_r, useful = [], [], [], [], []
+        for s_ in srcs:
+            _, st = sp.solve(G, [s_], rule="rho", rho=rho, tuning=tun, out=out)
+            if s_ not in m_reach_of:
+                m_reach_of[s_] = reachable_arcs(g, sp.to_numpy_u64(out)[0])
+            times.append(st["device_ms"])
+            balg.append(algorithmic_bytes(g.n, st, 1))
+            edges_r.append(st["edges_relaxed"])
+            steps_r.append(st["steps"])
+            useful.append(m_reach_of[s_])
+        ms = float(np.mean(times))
+        r = {"rho": rho, "ms": round(ms, 4), "steps": int(np.mean(steps_r)),
+             "edges_relaxed": int(np.mean(edges_r)),
+             "gteps": round(float(np.mean(edges_r)) / (ms * 1e6), 4),
+             "gteps_useful": round(float(np.mean(useful)) / (ms * 1e6), 4),
+             "roofline_frac": round(float(np.mean(balg)) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        if tun:
+            r["hub_defer"] = {"degree": tun["hub_defer_degree"], "div": tun["hub_defer_div"]}
+        log(f"  sweep rho=2^{rho.bit_length() - 1} {tun or ''}: {ms:.3f} ms, steps {r['steps']}, "
+            f"E_r {r['edges_relaxed']}, frac {r['roofline_frac']}")
+        return r
+
     if rule == "rho":
         if args.workload == "grid256":
             choices = [4096]
@@ -290,28 +328,26 @@ def run_single(args, torch, sp, w):
         else:
             choices = []
         for rho in choices:
-            # One solve per source (the timed solves' sources), averaged.
-            times, balg, edges_r, steps_r, useful = [], [], [], [], []
-            for s_ in srcs:
-                _, st = sp.solve(G, [s_], rule="rho", rho=rho, out=out)
-                if s_ not in m_reach_of:
-                    m_reach_of[s_] = reachable_arcs(g, sp.to_numpy_u64(out)[0])
-                times.append(st["device_ms"])
-                balg.append(algorithmic_bytes(g.n, st, 1))
-                edges_r.append(st["edges_relaxed"])
-                steps_r.append(st["steps"])
-                useful.append(m_reach_of[s_])
-            ms = float(np.mean(times))
-            sweep.append({"rho": rho, "ms": round(ms, 4), "steps": int(np.mean(steps_r)),
-                          "edges_relaxed": int(np.mean(edges_r)),
-                          "gteps": round(float(np.mean(edges_r)) / (ms * 1e6), 4),
-                          "gteps_useful": round(float(np.mean(useful)) / (ms * 1e6), 4),
-                          "roofline_frac": round(float(np.mean(balg)) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
-            log(f"  sweep rho=2^{rho.bit_length() - 1}: {ms:.3f} ms, steps {sweep[-1]['steps']}, "
-                f"E_r {sweep[-1]['edges_relaxed']}, frac {sweep[-1]['roofline_frac']}")
+            sweep.append(sweep_point(rho, None))
         fixed = {"rho": min(sweep, key=lambda r: r["ms"])["rho"] if sweep else (args.rho or 1 << 18)}
         if args.rho:
             fixed = {"rho": args.rho}
+        if args.defer:
+            deg, div = (int(x) for x in args.defer.split(","))
+            tuning = {"hub_defer_degree": deg, "hub_defer_div": div}
+        elif sweep and args.defer_sweep and args.workload == "rmat24":
+            # Hub deferral: the autotuner's candidates around the fastest rho
+            # of the paper's rule; the timed solves use the fastest of all.
+            from paper_2105_06145_amd import autotune as at
+            for rho, deg, div in at.defer_candidates(fixed["rho"]):
+                defer_sweep.append(sweep_point(rho, {"hub_defer_degree": deg, "hub_defer_div": div}))
+            best_d = min(defer_sweep, key=lambda r: r["ms"])
+            if best_d["ms"] < min(sweep, key=lambda r: r["ms"])["ms"] and not args.rho:
+                fixed = {"rho": best_d["rho"]}
+                tuning = {"hub_defer_degree": best_d["hub_defer"]["degree"],
+                          "hub_defer_div": best_d["hub_defer"]["div"]}
+        if tuning:
+            fixed["tuning"] = tuning
     else:
         fixed = {"delta": args.delta or int(w.params["delta"])}
 
@@ -354,7 +390,7 @@ def run_single(args, torch, sp, w):
         m_reach += m_reach_of[s_]
 
     roofline = roofline_entry(b_alg / args.steps, kernel_ms / args.steps,
-                              load_traffic(args.workload, fixed.get("rho", 0)))
+                              load_traffic(args.workload, traffic_key(fixed.get("rho", 0), tuning)))
     roofline["implementation_bytes_per_launch"] = int(b_impl / args.steps)
     copy_gbs = stream_copy_gbs(torch)
     roofline["stream_copy_gbs"] = round(copy_gbs, 1)
@@ -369,7 +405,10 @@ def run_single(args, torch, sp, w):
 
     config = {"workload": WORKLOADS[args.workload], "n": g.n, "m": g.m,
               "sources": srcs if len(srcs) > 1 else src, "rule": rule,
-              **fixed, "steps_per_solve": int(steps_total // args.steps),
+              **{k: v for k, v in fixed.items() if k != "tuning"},
+              "hub_defer": ({"degree": tuning["hub_defer_degree"], "div": tuning["hub_defer_div"]}
+                            if tuning else None),
+              "steps_per_solve": int(steps_total // args.steps),
               "edges_relaxed_per_solve": int(edges // args.steps),
               "writemin_success_per_solve": int(successes // args.steps),
               "useful_arcs_per_solve": int(m_reach // args.steps)}
@@ -381,7 +420,17 @@ def run_single(args, torch, sp, w):
         best = min(sweep, key=lambda r: r["ms"])
         res["rho_sweep"] = {"per_rho": sweep, "fastest_rho": best["rho"],
                             "fastest_frac": best["roofline_frac"],
-                            "what": "one solve per source per rho, averaged; the timed solves use the fastest rho"}
+                            "what": "the paper's rho rule: one solve per source per rho, averaged"}
+        res["paper_rule"] = {k: best[k] for k in ("rho", "ms", "steps", "edges_relaxed", "gteps", "gteps_useful",
+                                                  "roofline_frac")}
+    if defer_sweep:
+        bd = min(defer_sweep, key=lambda r: r["ms"])
+        res["hub_defer_sweep"] = {
+            "per_setting": defer_sweep, "fastest": {k: bd[k] for k in ("rho", "hub_defer", "ms")},
+            "what": ("rho with hub deferral (vertices of out-degree >= degree extracted only at keys up to the "
+                     "sampled (rho / div)-th key), one solve per source each; the timed solves use the fastest "
+                     "configuration of both sweeps (fewer arcs relaxed for the same distances, so GTEPS and the "
+                     "roofline fraction count less work)")}
     G.close()
     torch.cuda.synchronize()
     return res
@@ -789,6 +838,10 @@ def main():
     ap.add_argument("--sweep", default="16,17,18,19,20,21,22", metavar="LOG2_LIST",
                     help="rho values (log2) timed first, one solve per source each; the timed solves use the "
                          "fastest ('' = no sweep)")
+    ap.add_argument("--defer", default="", metavar="DEGREE,DIV",
+                    help="hub deferral for the timed solves (skips the deferral sweep)")
+    ap.add_argument("--no-defer-sweep", dest="defer_sweep", action="store_false",
+                    help="time the fastest rho of the paper's rule only")
     ap.add_argument("--no-ceilings", action="store_true",
                     help="rmat24: skip the gather / atomic-minimum ceiling microbenchmarks")
     ap.add_argument("--cpu-runs", type=int, default=3, help="timed runs of the CPU oracle (the median is reported)")

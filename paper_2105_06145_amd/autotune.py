@@ -20,7 +20,12 @@ This module searches them by timing real solves on the device:
      rho) puts more hops into one step, and with the default budget the
      expansion then stops short of them and the steps multiply, so values
      up to four times the best are tried with budgets grown alike;
-  4. the hub-degree threshold, the size of the arc chunks hubs are cut into
+  4. on graphs with high-degree vertices (out-degree 32 and up) and the
+     rho rule, rho and hub deferral together: deferring the hubs to a much
+     smaller threshold removes most of their repeated relaxations, and the
+     larger rho it allows cuts the steps, so values up to four times the
+     best are tried with three (degree, divisor) settings;
+  5. the hub-degree threshold, the size of the arc chunks hubs are cut into
      (the tile shape of their relaxation), the explicit-list switch, then
      the queue structure (flat array or tournament tree, Sec. 4).
 
@@ -72,6 +77,22 @@ def local_candidates(v0: int) -> list[tuple[int, int]]:
     return [(v0, 2 * b), (2 * v0, 2 * b), (2 * v0, 4 * b), (4 * v0, 4 * b), (4 * v0, 8 * b)]
 
 
+# (hub_defer_degree, hub_defer_div) settings tried with rho.
+DEFER_SETTINGS = [(32, 1000), (64, 300), (128, 100)]
+
+
+def defer_candidates(v0: int) -> list[tuple[int, int, int]]:
+    """(rho, hub_defer_degree, hub_defer_div) triples tried around the best
+    rho v0 found without deferral: v0, 2 * v0 and 4 * v0 with each setting."""
+    return [(v, deg, div) for v in (v0, 2 * v0, 4 * v0) for deg, div in DEFER_SETTINGS]
+
+
+def has_hubs(degree_log2_hist) -> bool:
+    """Whether a graph has vertices of out-degree 32 or more (its log2
+    out-degree histogram reaches bin 5)."""
+    return len(degree_log2_hist or []) > 5 and any(degree_log2_hist[5:])
+
+
 def relaxes_locally(n: int, m: int) -> bool:
     """Whether the library runs local expansion on a graph of this size
     (average out-degree below the super-sparse threshold)."""
@@ -87,8 +108,8 @@ def team_candidates(nsrc: int, grid: int = 1024) -> list[int]:
 
 
 class Tuner:
-    """Coordinate search over (rule parameter, teams, local_budget,
-    hub_degree, chunk_edges, list_divisor, queue).
+    """Coordinate search over (rule parameter, teams, local_budget, hub
+    deferral, hub_degree, chunk_edges, list_divisor, queue).
 
     `measure(config) -> ms` times one configuration; by default it runs the
     solver on the given graph and sources. A config is a dict with keys rule,
@@ -138,7 +159,7 @@ class Tuner:
         return ms
 
     def search(self, n: int, nsrc: int, w_median: int, rules=("rho", "delta"), grid: int = 1024,
-               local: bool = False) -> dict:
+               local: bool = False, hubs: bool = False) -> dict:
         t0 = time.monotonic()
         best = [None, math.inf]
 
@@ -180,7 +201,14 @@ class Tuner:
                 if out_of_time():
                     break
                 self._eval({"rule": name, name: v, "tuning": {**base_tuning, "local_budget": budget}}, best)
-        # 2., 4. kernel knobs, one at a time around the best so far.
+        # 4. rho and hub deferral together.
+        if hubs and best[0] is not None and best[0]["rule"] == "rho":
+            for v, deg, div in defer_candidates(best[0]["rho"]):
+                if out_of_time():
+                    break
+                tun = {**best[0].get("tuning", {}), "hub_defer_degree": deg, "hub_defer_div": div}
+                self._eval({"rule": "rho", "rho": v, "tuning": tun}, best)
+        # 2., 5. kernel knobs, one at a time around the best so far.
         knobs = []
         if nsrc > 1:
             knobs.append(("teams", team_candidates(nsrc, grid)))
@@ -223,7 +251,8 @@ class Tuner:
                 return times[len(times) // 2]
             self._measure = measure
         w_median = graph.summary.get("weight_q10_50_90", [0, 1, 0])[1] or 1
-        cfg = self.search(graph.n, nsrc, w_median, rules, local=relaxes_locally(graph.n, getattr(graph, "m", 0)))
+        cfg = self.search(graph.n, nsrc, w_median, rules, local=relaxes_locally(graph.n, getattr(graph, "m", 0)),
+                          hubs=has_hubs(graph.summary.get("degree_log2_hist")))
         self._store(self.key(fp, nsrc), cfg)
         return cfg
 

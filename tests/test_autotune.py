@@ -115,6 +115,35 @@ def test_local_budget_searched_with_delta():
     assert all("local_budget" not in c.get("tuning", {}) for c, _ in tu2.history)
 
 
+def defer_model(cfg):
+    """rho-stepping on a power-law graph: without deferral the best rho is
+    2^14; deferring hubs of degree >= 64 with divisor 300 makes rho = 2^16
+    best."""
+    if cfg["rule"] != "rho":
+        return 1000.0
+    lg = math.log2(cfg["rho"])
+    t = cfg.get("tuning", {})
+    if t.get("hub_defer_degree") == 64 and t.get("hub_defer_div") == 300:
+        return 8 + (lg - 16) ** 2
+    if t.get("hub_defer_degree"):
+        return 9.5 + (lg - 15) ** 2
+    return 10 + (lg - 14) ** 2
+
+
+def test_hub_deferral_searched_with_rho():
+    assert at.defer_candidates(1 << 10)[:3] == [(1 << 10, 32, 1000), (1 << 10, 64, 300), (1 << 10, 128, 100)]
+    assert len(at.defer_candidates(1 << 10)) == 9 and at.defer_candidates(8)[-1] == (32, 128, 100)
+    assert at.has_hubs([0, 1, 2, 3, 4, 5]) and not at.has_hubs([9, 9, 9, 9, 9]) and not at.has_hubs(None)
+    tu = at.Tuner(measure=defer_model)
+    cfg = tu.search(n=1 << 20, nsrc=1, w_median=1, rules=("rho",), hubs=True)
+    assert cfg["rho"] == 1 << 16 and cfg["tuning"]["hub_defer_degree"] == 64
+    assert cfg["tuning"]["hub_defer_div"] == 300 and cfg["ms"] == pytest.approx(8.0)
+    tu2 = at.Tuner(measure=defer_model)
+    cfg2 = tu2.search(n=1 << 20, nsrc=1, w_median=1, rules=("rho",))
+    assert cfg2["rho"] == 1 << 14
+    assert all("hub_defer_degree" not in c.get("tuning", {}) for c, _ in tu2.history)
+
+
 def test_cache_round_trip(tmp_path):
     path = str(tmp_path / "tune.json")
     tu = at.Tuner(cache_path=path, measure=cost_model)
