@@ -648,9 +648,17 @@ def run_serve(args, torch, sp):
         # group of k teams uses k times them): the whole-grid values divided
         # by the server's team count, so a request that arrives at a quiet
         # server, solved by all its teams, runs with the plain loop's values.
-        cfg_p = [{"rule": "rho", "rho": 1 << 17, "tuning": {}}, {"rule": "delta", "delta": 67584, "tuning": {}}]
+        # R-MAT: rho = 2^19 with hub deferral (degree 64, rank rho / 300),
+        # 6.7 against 9.6 ms per query for the paper's rule at its best rho
+        # (2^17) on the whole grid; --serve-no-defer keeps the paper's rule.
+        if args.serve_defer:
+            rmat_rho, rmat_tun = 1 << 19, {"hub_defer_degree": 64, "hub_defer_div": 300}
+        else:
+            rmat_rho, rmat_tun = 1 << 17, {}
+        cfg_p = [{"rule": "rho", "rho": rmat_rho, "tuning": dict(rmat_tun)},
+                 {"rule": "delta", "delta": 67584, "tuning": {}}]
         nteams = [int(x) for x in args.serve_teams.split(",")]
-        cfg_s = [{"rule": "rho", "rho": args.serve_rho or max(1, (1 << 17) // nteams[0]), "tuning": {}},
+        cfg_s = [{"rule": "rho", "rho": args.serve_rho or max(1, rmat_rho // nteams[0]), "tuning": dict(rmat_tun)},
                  {"rule": "delta", "delta": args.serve_delta or max(1, 67584 // nteams[1]), "tuning": {}}]
     for k in ((0, 1) if args.tune_budget > 0 else ()):
         ks = [int(x) for x in src[which == k][:32]]
@@ -870,6 +878,8 @@ def main():
                     help="serving: the R-MAT server's rho per team (0 = 2^17 / its teams)")
     ap.add_argument("--serve-delta", type=int, default=0,
                     help="serving: the grid server's Delta per team (0 = 67584 / its teams)")
+    ap.add_argument("--serve-no-defer", dest="serve_defer", action="store_false",
+                    help="serving: the paper's rho rule for the R-MAT queries (default: hub deferral)")
     ap.add_argument("--oracle-sample", type=int, default=4, help="serving: queries per graph checked by the oracle")
     ap.add_argument("--tune-budget", type=float, default=20.0,
                     help="seconds of parameter search per mode for the batched and serving workloads "
