@@ -95,7 +95,11 @@ struct sssp_graph {
   sssp_impl::DevBuf lastkey, ckey, cbase;
   void* hargs = nullptr;  // host staging copy of the kernel arguments (operator new)
 
-  uint64_t graph_bytes() const { return off.bytes + edges.bytes + perm.bytes + inv.bytes; }
+  // Local expansion: per arc, the packed row of its target (built on the
+  // first launch with local expansion).
+  sssp_impl::DevBuf trow;
+
+  uint64_t graph_bytes() const { return off.bytes + edges.bytes + perm.bytes + inv.bytes + trow.bytes; }
   uint64_t workspace_bytes() const {
     return dist_int.bytes + bitmap.bytes + hint.bytes + tree.bytes + hubmask.bytes + bigmask.bytes + F.bytes + FD.bytes + H.bytes + L.bytes + samples.bytes +
            parts.bytes + ctl.bytes + args.bytes + srcs.bytes + lastkey.bytes + ckey.bytes + cbase.bytes;
@@ -118,6 +122,7 @@ struct sssp_graph {
     src_host_cap = 0;
     off.release(nullptr);
     edges.release(nullptr);
+    trow.release(nullptr);
     perm.release(nullptr);
     inv.release(nullptr);
     ::operator delete(hargs);

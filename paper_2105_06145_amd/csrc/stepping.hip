@@ -92,6 +92,8 @@ constexpr int BLOCK_WORDS = 4;  // bitmap words per ownership block (256 vertice
 // The word-per-wave Extract gives wave w word w of each block it owns.
 static_assert(BLOCK_WORDS == WAVES, "one wave per bitmap word of a block");
 constexpr int LQ = 1024;        // local-expansion list capacity per round (LDS)
+constexpr int ROW_SHIFT = 40;   // packed row: (degree << ROW_SHIFT) | row start
+constexpr ull ROW_START = (1ull << ROW_SHIFT) - 1;
 
 // ---------------------------------------------------------------------------
 // Control blocks.
@@ -205,6 +207,9 @@ struct KArgs {
   ull* ckey;            // per team, hcap: the same per hub chunk (NULL: off)
   const uint32_t* cbase;  // hub u < nhub: index of u's first chunk in ckey (hubs are numbered first)
   uint64_t nhub;
+  const ull* trow;      // per arc: (degree << ROW_SHIFT) | row start of its target, for local
+                        // expansion (NULL: the next round reads the offsets)
+  uint32_t local_cap;   // out-degree above which a vertex is not relaxed by local expansion
   uint64_t ndefer;      // sampled rho steps: vertices below this id (the highest degrees, numbered
                         // first) are extracted only at keys <= theta_h (0: no deferral)
   uint64_t defer_div;   // theta_h is the sampled (rho / defer_div)-th smallest key
@@ -266,7 +271,11 @@ struct Shared {
   uint32_t wsum[WAVES];
   ull red[WAVES * 4];
   ull bcast[4];
-  int32_t lq[2][LQ];  // local expansion: this round's vertices and the next round's
+  // Local expansion: this round's vertices and the next round's, each with
+  // its packed row (or INF: read the offsets).
+  int32_t lq[2][LQ];
+  ull lqr[2][LQ];
+  int32_t uid[WG];  // the tile's vertices (their keys are read per arc in row mode)
   uint32_t lqn[2];
   uint32_t fcnt;  // F entries reserved by this workgroup in a bitmap step
   ull hub_task, hub_du;  // the hub chunk in hand and the key it is pushed with
@@ -1267,7 +1276,7 @@ struct Local {
 // to the next explicit list when it is being built.
 __device__ __forceinline__ void relax_batch(const KArgs& a, const Team& tm, ull* dist, StepSlot* S, int32_t* Lnext,
                                             bool emit, RelaxAcc& acc, const Local& lx, const ull (&ev)[UNROLL],
-                                            const ull (&dd)[UNROLL]) {
+                                            const ull (&dd)[UNROLL], const ull (&tr)[UNROLL]) {
   Shared& sh = g_sh;
   int32_t fv[UNROLL];
   uint32_t hv[UNROLL];
@@ -1318,10 +1327,12 @@ __device__ __forceinline__ void relax_batch(const KArgs& a, const Team& tm, ull*
     // high-degree vertex in one workgroup's list would serialise its arcs
     // there).
     if (lx.on && nd[k] <= lx.theta && (ull)(uint32_t)fv[k] >= a.ndefer &&
-        !((ld_plain(&a.bigmask[fv[k] >> 6]) >> (fv[k] & 63)) & 1ull)) {
+        (tr[k] != INF ? (tr[k] >> ROW_SHIFT) <= a.local_cap
+                      : !((ld_plain(&a.bigmask[fv[k] >> 6]) >> (fv[k] & 63)) & 1ull))) {
       const uint32_t slot = atomicAdd(&sh.lqn[lx.nxt], 1u);
       if (slot < (uint32_t)LQ) {
         sh.lq[lx.nxt][slot] = fv[k];
+        sh.lqr[lx.nxt][slot] = tr[k];
         continue;
       }
     }
@@ -1355,15 +1366,22 @@ __device__ __forceinline__ void relax_batch(const KArgs& a, const Team& tm, ull*
 // than repeat the last arc's.
 template <bool Sparse>
 __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* dist, StepSlot* S, int32_t* Lnext,
-                                           bool emit, RelaxAcc& acc, const Local& lx, int32_t u, ull du) {
+                                           bool emit, RelaxAcc& acc, const Local& lx, int32_t u, ull du, ull row,
+                                           bool rows) {
   Shared& sh = g_sh;
   const unsigned tid = threadIdx.x;
   const ArcSrc arcs{a.edges, a.tgt, a.wt};
   uint32_t deg = 0;
   ull rb = 0;
   if (u >= 0) {
-    rb = (ull)*glob(&a.off[u]);
-    deg = (uint32_t)((ull)*glob(&a.off[u + 1]) - rb);
+    if (row != INF) {
+      // Local expansion: the row came with the arc that queued u.
+      rb = row & ROW_START;
+      deg = (uint32_t)(row >> ROW_SHIFT);
+    } else {
+      rb = (ull)*glob(&a.off[u]);
+      deg = (uint32_t)((ull)*glob(&a.off[u + 1]) - rb);
+    }
     if (tm.lastkey) {
       // u's arcs were already pushed with this very key: every WriteMin
       // would fail, so they are not pushed again.
@@ -1382,6 +1400,7 @@ __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* 
   sh.beg[tid] = rb;
   sh.du[tid] = du;
   sh.pulled[tid] = du;
+  sh.uid[tid] = u;
   __syncthreads();
   if (a.pull) {
     // Bidirectional relaxation (Sec. 6): first lower each vertex's key with
@@ -1416,10 +1435,11 @@ __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* 
     __syncthreads();
   }
   for (uint32_t e0 = 0; e0 < total; e0 += WG * UNROLL) {
-    ull ev[UNROLL], dd[UNROLL];
+    ull ev[UNROLL], dd[UNROLL], tr[UNROLL];
 #pragma unroll
     for (int k = 0; k < UNROLL; ++k) {
       const uint32_t e = e0 + k * WG + tid;
+      tr[k] = INF;
       if constexpr (Sparse) {
         ev[k] = INF;
         dd[k] = 0;
@@ -1428,8 +1448,16 @@ __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* 
 #pragma unroll
           for (int step = WG / 2; step > 0; step >>= 1)
             if (sh.pre[lo + step] <= e) lo += step;
-          ev[k] = arcs.at(sh.beg[lo] + (e - sh.pre[lo]));
-          dd[k] = sh.du[lo];
+          const ull idx = sh.beg[lo] + (e - sh.pre[lo]);
+          ev[k] = arcs.at(idx);
+          if (rows) {
+            // Row mode: each arc carries its target's row to the LDS list,
+            // and its tail's current key is read beside the arc.
+            tr[k] = *glob(&a.trow[idx]);
+            dd[k] = ld_agent(&dist[sh.uid[lo]]);
+          } else {
+            dd[k] = sh.du[lo];
+          }
         }
       } else {
         // Lanes past the tile's end read its last arc and drop it: the reads
@@ -1444,7 +1472,7 @@ __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* 
         dd[k] = sh.du[lo];
       }
     }
-    relax_batch(a, tm, dist, S, Lnext, emit, acc, lx, ev, dd);
+    relax_batch(a, tm, dist, S, Lnext, emit, acc, lx, ev, dd, tr);
   }
   __syncthreads();
 }
@@ -1524,7 +1552,7 @@ __device__ __forceinline__ RelaxAcc relax_hub_chunks(const KArgs& a, ull* dist, 
       if (tid == 0 && tm.ckey && (ull)u < a.nhub) tm.ckey[a.cbase[u] + c] = du;
     }
     for (ull e0 = beg; e0 < end; e0 += (ull)WG * UNROLL) {
-      ull ev[UNROLL], dd[UNROLL];
+      ull ev[UNROLL], dd[UNROLL], tr[UNROLL];
 #pragma unroll
       for (int k = 0; k < UNROLL; ++k) {
         // A chunk is never empty; lanes past its end read its last arc and
@@ -1533,8 +1561,9 @@ __device__ __forceinline__ RelaxAcc relax_hub_chunks(const KArgs& a, ull* dist, 
         const ull arc = arcs.at(e < end ? e : end - 1);
         ev[k] = e < end ? arc : INF;
         dd[k] = du;
+        tr[k] = INF;
       }
-      relax_batch(a, tm, dist, S, Lnext, emit, acc, lx, ev, dd);
+      relax_batch(a, tm, dist, S, Lnext, emit, acc, lx, ev, dd, tr);
     }
   }
   return acc;
@@ -1567,19 +1596,31 @@ __device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S,
   uint32_t cnt = ex.fcnt, cur = 1;
   ull done_local = 0;
   const bool sparse_graph = __builtin_amdgcn_readfirstlane(a.local_budget > 0 ? 1 : 0) != 0;
+  // Row mode (local expansion with target rows, keys read per arc): a listed
+  // vertex needs no offset or key read before its round. Not with the
+  // repeated-push skip or bidirectional relaxation, which need u's key
+  // up front.
+  const bool rows = sparse_graph && local && a.trow != nullptr && tm.lastkey == nullptr && !a.pull;
   for (bool first = true;; first = false) {
     for (uint32_t j0 = 0; j0 < cnt; j0 += WG) {
       const uint32_t j = j0 + tid;
       int32_t u = -1;
-      ull du = 0;
+      ull du = 0, row = INF;
       if (j < cnt) {
-        u = first ? tm.Fb[j] : sh.lq[cur][j];
-        du = (first && a.snapshot) ? tm.FDb[j] : ld_agent(&dist[u]);
+        if (first) {
+          u = tm.Fb[j];
+          du = a.snapshot ? tm.FDb[j] : ld_agent(&dist[u]);
+        } else {
+          // A listed vertex's row came with the arc that listed it.
+          u = sh.lq[cur][j];
+          if (rows) row = sh.lqr[cur][j];
+          if (row == INF) du = ld_agent(&dist[u]);
+        }
       }
       if (sparse_graph)
-        relax_tile<true>(a, tm, dist, S, Lnext, emit, acc, lx, u, du);
+        relax_tile<true>(a, tm, dist, S, Lnext, emit, acc, lx, u, du, row, rows);
       else
-        relax_tile<false>(a, tm, dist, S, Lnext, emit, acc, lx, u, du);
+        relax_tile<false>(a, tm, dist, S, Lnext, emit, acc, lx, u, du, row, false);
     }
     if (!local) break;
     cur = lx.nxt;
@@ -2754,11 +2795,38 @@ void fill_args(const sssp_graph* g, Launch& L, const WsView& w, uint64_t* dist) 
   if ((uint64_t)g->m >= (uint64_t)tu.super_sparse_degree * (uint64_t)g->n) a.local_budget = 0;
   // Bidirectional relaxation reads current keys too; it needs symmetric arcs.
   a.pull = (!a.snapshot && g->undirected && tu.pull != 0xFFFFFFFFu && tu.pull != 0) ? 1u : 0u;
+  // Local expansion admits vertices up to this out-degree (the packed rows
+  // hold degrees below 2^24 - 1).
+  a.local_cap = std::min<uint32_t>(local_degree_cap(tu), (1u << 24) - 2u);
   // Hub deferral (rho rule): on a graph numbered by degree the vertices of
   // out-degree at least 2^k are the ids below deg_ge[k].
   a.defer_div = tu.hub_defer_div ? tu.hub_defer_div : 10u;
   if (p.rule == SSSP_RULE_RHO && g->relabelled && tu.hub_defer_degree != 0 && tu.hub_defer_degree != 0xFFFFFFFFu)
     a.ndefer = g->deg_ge[31 - __builtin_clz(tu.hub_defer_degree)];
+}
+
+// trow[e] = (degree << ROW_SHIFT) | row start of arc e's target, degree
+// saturated at 2^24 - 1.
+__global__ void target_rows_kernel(const int64_t* off, const ull* edges, const int32_t* tgt, ull m, ull* trow) {
+  for (ull e = (ull)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (ull)gridDim.x * blockDim.x) {
+    const uint32_t t = edges ? (uint32_t)edges[e] : (uint32_t)tgt[e];
+    const ull rb = (ull)off[t], deg = (ull)off[t + 1] - rb;
+    trow[e] = (umin(deg, (1ull << 24) - 1) << ROW_SHIFT) | rb;
+  }
+}
+
+// The graph's target rows for local expansion (8 bytes per arc), built on
+// the first launch that can use them. Not for borrowed arrays (the caller
+// may rewrite them between solves), nor beyond 2^40 arcs; the kernel then
+// reads the offsets.
+sssp_status ensure_target_rows(sssp_graph* g, hipStream_t st) {
+  const ull m = (ull)g->m;
+  if (g->trow.p || g->borrowed || m == 0 || m > ROW_START) return SSSP_OK;
+  SSSP_HIP_TRY(g->trow.alloc(m * 8, st));
+  target_rows_kernel<<<2048, 256, 0, st>>>((const int64_t*)g->off.p, g->borrowed ? nullptr : (const ull*)g->edges.p,
+                                          g->btgt, m, (ull*)g->trow.p);
+  SSSP_HIP_TRY(hipGetLastError());
+  return SSSP_OK;
 }
 
 // Plan the launch, make sure the graph's workspace fits it, and fill the
@@ -2777,6 +2845,11 @@ sssp_status prepare_launch(sssp_graph* g, Launch& L, uint32_t default_teams, uin
   s = ensure_workspace(g, L.tu, L.geo, repeat, st);
   if (s != SSSP_OK) return s;
   fill_args(g, L, graph_view(g), dist);
+  if (L.a.local_budget > 0) {
+    s = ensure_target_rows(g, st);
+    if (s != SSSP_OK) return s;
+    L.a.trow = (const ull*)g->trow.p;
+  }
   if (repeat) {
     L.a.lastkey = (ull*)g->lastkey.p;
     if (g->relabelled && g->nhub > 0) {

@@ -232,6 +232,35 @@ def test_local_expansion_on_road_graphs(sp):
     G.close()
 
 
+def test_local_expansion_row_mode_and_its_fallbacks(sp, torch_cuda):
+    """Local expansion lists carry each vertex's row from the arc that
+    listed it (row mode); without those rows (borrowed arrays), with the
+    repeated-push skip, with more teams and with a budget that overflows the
+    LDS lists, the next round reads the offsets. Every form gives the
+    oracle's distances."""
+    import torch
+    g = graphgen.road(150, 150, seed=29)
+    srcs = [11, 9000, 20000]
+    exp = [ref(g, s) for s in srcs]
+    G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
+    off_d = torch.from_numpy(g.offsets.astype(np.int64)).cuda()
+    tgt_d = torch.from_numpy(g.targets.astype(np.int32)).cuda()
+    wt_d = torch.from_numpy(g.weights.astype(np.uint32).view(np.int32)).cuda()
+    B = sp.Graph.from_csr(off_d, tgt_d, wt_d, borrow=True)
+    try:
+        for graph, name in ((G, "copied"), (B, "borrowed")):
+            for tun in ({}, {"repeat_skip": 1}, {"teams": 8}, {"local_budget": 1 << 16, "super_sparse_degree": 1 << 20},
+                        {"local_budget": 3}):
+                for rule, kw in (("delta", {"delta": 3000}), ("rho", {"rho": 128})):
+                    d, st = sp.solve(graph, srcs, rule=rule, tuning=tun or None, **kw)
+                    got = sp.to_numpy_u64(d)
+                    for i, s in enumerate(srcs):
+                        assert_same(got[i], exp[i], f"{name} {tun} {rule} source {s}")
+    finally:
+        G.close()
+        B.close()
+
+
 def test_bidirectional_relaxation(sp):
     """Pull-then-push relaxation (Sec. 6) on symmetric graphs leaves every
     distance as it is; it is refused on graphs not declared undirected, and
