@@ -92,6 +92,7 @@ constexpr int BLOCK_WORDS = 4;  // bitmap words per ownership block (256 vertice
 // The word-per-wave Extract gives wave w word w of each block it owns.
 static_assert(BLOCK_WORDS == WAVES, "one wave per bitmap word of a block");
 constexpr int LQ = 1024;        // local-expansion list capacity per round (LDS)
+constexpr int PEND = 1024;      // Relax's appends to the next explicit list, staged in LDS
 constexpr int ROW_SHIFT = 40;   // packed row: (degree << ROW_SHIFT) | row start
 constexpr ull ROW_START = (1ull << ROW_SHIFT) - 1;
 
@@ -276,6 +277,10 @@ struct Shared {
   int32_t lq[2][LQ];
   ull lqr[2][LQ];
   int32_t uid[WG];  // the tile's vertices (their keys are read per arc in row mode)
+  // Relax's new queue members for the next explicit list, written out once
+  // per step (pend_flush) instead of with a workgroup reservation per batch.
+  int32_t pend[PEND];
+  uint32_t npend;
   uint32_t lqn[2];
   uint32_t fcnt;  // F entries reserved by this workgroup in a bitmap step
   ull hub_task, hub_du;  // the hub chunk in hand and the key it is pushed with
@@ -749,6 +754,48 @@ __device__ __forceinline__ void list_append(const KArgs& a, StepSlot* S, int32_t
       if (o < a.lcap) Lnext[o] = v[k];
       ++o;
     }
+}
+
+// Stage v in this workgroup's LDS buffer for the next explicit list (any
+// lanes; no barrier); a full buffer sends the entry straight to the list.
+__device__ __forceinline__ void pend_push(const KArgs& a, StepSlot* S, int32_t* Lnext, int32_t v) {
+  Shared& sh = g_sh;
+  const uint32_t slot = atomicAdd(&sh.npend, 1u);
+  if (slot < (uint32_t)PEND) {
+    sh.pend[slot] = v;
+  } else {
+    const ull o = atom_add(&S->list_next, 1ull);
+    if (o < a.lcap) Lnext[o] = v;
+  }
+}
+
+// Write the staged entries to the next explicit list with one reservation
+// and clear the buffer. Whole workgroup, uniform call.
+__device__ __forceinline__ void pend_flush(const KArgs& a, StepSlot* S, int32_t* Lnext) {
+  Shared& sh = g_sh;
+  __syncthreads();  // every staged entry written
+  // Uniform: nothing is staged between the barrier above and the next one.
+  const uint32_t n = min(sh.npend, (uint32_t)PEND);
+  if (n == 0) return;
+  if (threadIdx.x == 0) sh.bcast[0] = atom_add(&S->list_next, (ull)n);
+  __syncthreads();
+  const ull base = sh.bcast[0];
+  for (uint32_t i = threadIdx.x; i < n; i += WG)
+    if (base + i < a.lcap) Lnext[base + i] = sh.pend[i];
+  __syncthreads();
+  if (threadIdx.x == 0) sh.npend = 0;
+  __syncthreads();
+}
+
+// Between batches of a long tile or hub chunk: flush once the buffer is
+// half full (a batch stages at most WG * UNROLL entries, so it rarely
+// overflows). Whole workgroup, uniform call.
+__device__ __forceinline__ void pend_check(const KArgs& a, StepSlot* S, int32_t* Lnext) {
+  Shared& sh = g_sh;
+  __syncthreads();
+  const bool full = sh.npend > (uint32_t)PEND / 2;
+  __syncthreads();  // every thread has read the count before anyone stages more
+  if (full) pend_flush(a, S, Lnext);
 }
 
 // Sample size and probe count of a rho step (App. B: s = c (q / rho + log q),
@@ -1280,7 +1327,6 @@ __device__ __forceinline__ void relax_batch(const KArgs& a, const Team& tm, ull*
   Shared& sh = g_sh;
   int32_t fv[UNROLL];
   uint32_t hv[UNROLL];
-  unsigned mask = 0;
   // The batch's key-bound reads first, all in flight together: no branch
   // around a read (an absent arc reads hint[0]), and a wave-uniform switch,
   // because a load under a divergent branch makes the compiler wait for
@@ -1353,9 +1399,8 @@ __device__ __forceinline__ void relax_batch(const KArgs& a, const Team& tm, ull*
   for (int k = 0; k < UNROLL; ++k)
     if (((upd >> k) & 1u) && !((ow[k] >> (fv[k] & 63)) & 1ull)) {
       ++acc.fresh;
-      mask |= 1u << k;
+      if (emit) pend_push(a, S, Lnext, fv[k]);
     }
-  if (emit) list_append(a, S, Lnext, fv, mask);
 }
 
 // Relax the arcs of up to WG vertices (one per thread; u < 0 for none, du its
@@ -1367,7 +1412,7 @@ __device__ __forceinline__ void relax_batch(const KArgs& a, const Team& tm, ull*
 template <bool Sparse>
 __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* dist, StepSlot* S, int32_t* Lnext,
                                            bool emit, RelaxAcc& acc, const Local& lx, int32_t u, ull du, ull row,
-                                           bool rows) {
+                                           bool rows, bool sync_after = true) {
   Shared& sh = g_sh;
   const unsigned tid = threadIdx.x;
   const ArcSrc arcs{a.edges, a.tgt, a.wt};
@@ -1473,8 +1518,11 @@ __device__ __forceinline__ void relax_tile(const KArgs& a, const Team& tm, ull* 
       }
     }
     relax_batch(a, tm, dist, S, Lnext, emit, acc, lx, ev, dd, tr);
+    if (emit && e0 + WG * UNROLL < total) pend_check(a, S, Lnext);
   }
-  __syncthreads();
+  // The tile arrays are reused by the next tile (the caller may end the
+  // round with a barrier of its own instead).
+  if (sync_after) __syncthreads();
 }
 
 // The team's hub chunks, strided over its workgroups. Each chunk is pushed
@@ -1564,6 +1612,7 @@ __device__ __forceinline__ RelaxAcc relax_hub_chunks(const KArgs& a, ull* dist, 
         tr[k] = INF;
       }
       relax_batch(a, tm, dist, S, Lnext, emit, acc, lx, ev, dd, tr);
+      if (emit) pend_check(a, S, Lnext);
     }
   }
   return acc;
@@ -1581,6 +1630,7 @@ __device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S,
   RelaxAcc acc{0, 0, 0, INF, 0, 0};
   Local lx{local, 0, theta};
   if (tid < 2) sh.lqn[tid] = 0;
+  if (tid == 0) sh.npend = 0;
   __syncthreads();
   {
     const RelaxAcc h = relax_hub_chunks(a, dist, S, Lnext, emit, lx);
@@ -1617,15 +1667,24 @@ __device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S,
           if (row == INF) du = ld_agent(&dist[u]);
         }
       }
+      // A local round's last tile leaves its barrier to the one below.
+      const bool sync_after = !(local && j0 + WG >= cnt);
       if (sparse_graph)
-        relax_tile<true>(a, tm, dist, S, Lnext, emit, acc, lx, u, du, row, rows);
+        relax_tile<true>(a, tm, dist, S, Lnext, emit, acc, lx, u, du, row, rows, sync_after);
       else
-        relax_tile<false>(a, tm, dist, S, Lnext, emit, acc, lx, u, du, row, false);
+        relax_tile<false>(a, tm, dist, S, Lnext, emit, acc, lx, u, du, row, false, sync_after);
+      // Read after the tile's barrier and before the next tile stages
+      // anything, so every thread sees the same count.
+      if (emit && sync_after && sh.npend > (uint32_t)PEND / 2) pend_flush(a, S, Lnext);
     }
     if (!local) break;
     cur = lx.nxt;
+    // The list read in the last round (cur ^ 1) receives the next round's
+    // vertices: its count is cleared before the barrier that publishes cur's.
+    if (tid == 0) sh.lqn[cur ^ 1u] = 0;
     __syncthreads();
     cnt = min(sh.lqn[cur], (uint32_t)LQ);
+    if (emit && sh.npend > (uint32_t)PEND / 2) pend_flush(a, S, Lnext);
     if (cnt == 0) break;
     {
       if (done_local + cnt > a.local_budget) {
@@ -1647,12 +1706,11 @@ __device__ __noinline__ void phase_relax(const KArgs& a, ull* dist, StepSlot* S,
         break;
       }
       done_local += cnt;
-      if (tid == 0) sh.lqn[cur ^ 1u] = 0;
-      __syncthreads();
       lx.nxt = cur ^ 1u;
     }
   }
   acc.local = done_local;
+  if (emit) pend_flush(a, S, Lnext);
   ull xs = ex.x, mk = ex.minkept;
   wg_reduce4(sh, acc.edges, acc.succ, acc.fresh, acc.minnew);
   {
