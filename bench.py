@@ -861,7 +861,7 @@ def main():
     ap.add_argument("--sources", type=int, default=10,
                     help="rmat24: seeded sources in the largest component; timed solve i uses source i mod K")
     ap.add_argument("--queries", type=int, default=600, help="serving: queries in the trace")
-    ap.add_argument("--latency-queries", type=int, default=200,
+    ap.add_argument("--latency-queries", type=int, default=1000,
                     help="rmat24: queries of the short serving run whose p50/p99 join the line (0 = skip)")
     ap.add_argument("--closed-queries", type=int, default=2000,
                     help="serving: queries of the closed-loop (saturation) runs, a prefix of the trace (0 = all)")
