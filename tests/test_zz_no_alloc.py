@@ -45,7 +45,13 @@ def test_noalloc_matches_solve_two_calls_second_smaller(sp, torch_cuda):
     N = sp._native
     big = graphgen.rmat(14, 16, whi=1 << 18, seed=71)
     small = graphgen.grid2d(40, 30, 1, 1 << 16, seed=72)
+    # Hub deferral on the power-law graph (its benchmark configuration), then
+    # the plain rho rule on it, then the small grid: local expansion, which
+    # the allocation-free call runs without the graph's target rows.
+    defer = N.sssp_tuning()
+    defer.hub_defer_degree, defer.hub_defer_div = 64, 300
     cases = [
+        (big, [5, 900], _params(sp, N.SSSP_RULE_RHO, rho=4096, seed=3, tuning=ctypes.pointer(defer))),
         (big, [5, 900, 16000], _params(sp, N.SSSP_RULE_RHO, rho=512, seed=3)),
         (small, [17], _params(sp, N.SSSP_RULE_DELTA_STAR, delta=5000)),
     ]
