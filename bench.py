@@ -698,6 +698,7 @@ def run_serve(args, torch, sp):
 
     serve_teams = [int(x) for x in args.serve_teams.split(",")]
     serve_bpc = [int(x) for x in args.serve_bpc.split(",")]
+    serve_gmax = [int(x) for x in args.serve_group_max.split(",")]
     # The admission budget, split between the two servers in proportion to
     # their grids.
     budget = int(args.serve_budget_gib * (1 << 30))
@@ -709,7 +710,8 @@ def run_serve(args, torch, sp):
         released as soon as it is polled); returns (latencies, hashes,
         makespan, stats, most rows in use)."""
         servers = [sp.BudgetServer(G[k], budgets[k], tuning={**(cfg_s[k].get("tuning") or {}),
-                                                             "blocks_per_cu": serve_bpc[k], "teams": serve_teams[k]},
+                                                             "blocks_per_cu": serve_bpc[k], "teams": serve_teams[k],
+                                                             "group_max": serve_gmax[k]},
                                    hash_rows=True, stream=side, **params(cfg_s[k])) for k in (0, 1)]
         ticket = [{}, {}]
         lat = np.zeros(count)
@@ -810,7 +812,7 @@ def run_serve(args, torch, sp):
         "config": {"workload": WORKLOADS["serve"], "queries": nq, "closed_loop_queries": nc,
                    "admission_budget_bytes": budgets, "result_rows": rowinfo["rows"],
                    "peak_rows_in_use": rowinfo["peak_rows_in_use"],
-                   "server_teams": serve_teams, "server_blocks_per_cu": serve_bpc,
+                   "server_teams": serve_teams, "server_blocks_per_cu": serve_bpc, "server_group_max": serve_gmax,
                    "served": [params(c) | {"tuning": c.get("tuning")} for c in cfg_s],
                    "plain": [params(c) | {"tuning": c.get("tuning")} for c in cfg_p]},
         "closed_loop": {"queries": nc, "plain_qps": round(rate_plain, 2), "served_qps": round(nc / span_s0, 2),
@@ -870,6 +872,10 @@ def main():
                          "proportion to their grids")
     ap.add_argument("--serve-bpc", default="2,2",
                     help="serving: workgroups per CU of the R-MAT and grid servers (sum at most 4)")
+    ap.add_argument("--serve-group-max", default="8,16",
+                    help="serving: most teams per request on the R-MAT and grid servers (0 = all of them; "
+                         "half of each server by default, so a request that arrives while another runs "
+                         "finds idle teams)")
     ap.add_argument("--serve-teams", default="16,32",
                     help="serving: teams of the R-MAT and grid servers (with --serve-bpc 2,2 on 256 CUs: 16 "
                          "R-MAT teams of 32 workgroups, 32 grid teams of 16); a request takes a group of "
