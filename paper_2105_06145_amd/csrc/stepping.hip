@@ -2875,12 +2875,19 @@ __global__ void target_rows_kernel(const int64_t* off, const ull* edges, const i
 
 // The graph's target rows for local expansion (8 bytes per arc), built on
 // the first launch that can use them. Not for borrowed arrays (the caller
-// may rewrite them between solves), nor beyond 2^40 arcs; the kernel then
-// reads the offsets.
+// may rewrite them between solves), nor beyond 2^40 arcs, nor when the
+// device has no room for them; the kernel then reads the offsets.
 sssp_status ensure_target_rows(sssp_graph* g, hipStream_t st) {
   const ull m = (ull)g->m;
   if (g->trow.p || g->borrowed || m == 0 || m > ROW_START) return SSSP_OK;
-  SSSP_HIP_TRY(g->trow.alloc(m * 8, st));
+  const hipError_t e = g->trow.alloc(m * 8, st);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();  // not kept: an optional array
+    g->trow.p = nullptr;
+    g->trow.bytes = 0;
+    return SSSP_OK;
+  }
+  SSSP_HIP_TRY(e);
   target_rows_kernel<<<2048, 256, 0, st>>>((const int64_t*)g->off.p, g->borrowed ? nullptr : (const ull*)g->edges.p,
                                           g->btgt, m, (ull*)g->trow.p);
   SSSP_HIP_TRY(hipGetLastError());
