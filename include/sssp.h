@@ -289,7 +289,8 @@ sssp_status sssp_graph_create(int64_t n, int64_t m, sssp_offset_width ow, const 
  * it or an asynchronous solve is pending (sssp_solve_wait first). */
 sssp_status sssp_graph_destroy(sssp_graph* g);
 
-/* Query sizes: vertices, arcs and device bytes held (graph plus workspace). */
+/* Query sizes: vertices, arcs and device bytes held (graph, with its per-arc
+ * target rows once built, plus workspace). */
 sssp_status sssp_graph_info(const sssp_graph* g, int64_t* n, int64_t* m, uint64_t* device_bytes);
 
 /*
@@ -448,7 +449,11 @@ sssp_status sssp_server_start(const sssp_graph* g, const sssp_params* params, ui
  * is counted first, and the rest holds floor(rest / (8 n)) result rows (at
  * most 65536), allocated here and owned by the server; the ring holds as many
  * entries as rows. OUT_OF_MEMORY when the budget holds no row (the detail
- * gives the workspace and row sizes). Other arguments as sssp_server_start. */
+ * gives the workspace and row sizes). The graph's own arrays are not part of
+ * the budget: its CSR, and on graphs with local expansion the per-arc target
+ * rows (8 bytes per arc) that the first launch builds (and skips, reading
+ * the offsets instead, when the device has no room for them); the graph
+ * holds them until it is destroyed. Other arguments as sssp_server_start. */
 sssp_status sssp_server_start_budget(const sssp_graph* g, const sssp_params* params, uint64_t budget_bytes,
                                      uint32_t flags, uint32_t idle_ms, void* stream, sssp_server** out);
 
