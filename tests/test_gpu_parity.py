@@ -658,7 +658,7 @@ def test_full_road5000_delta_star_and_bf(sp, road5000):
     exp = ref(g, s)
     G = sp.Graph.from_csr(g.offsets.astype(np.int32), g.targets, g.weights)
     for rule, kw in [("delta", {"delta": 1 << 10}), ("delta", {"delta": 1 << 15}), ("delta", {"delta": 1 << 16}),
-                     ("bf", {})]:
+                     ("delta", {"delta": 1 << 16, "tuning": {"local_budget": 8192}}), ("bf", {})]:
         dist, st = sp.solve(G, [s], rule=rule, **kw)
         got = sp.to_numpy_u64(dist)[0]
         assert_same(got, exp, f"road5000 {rule} {kw}")
@@ -675,7 +675,7 @@ def test_full_knn10000_batched_rows(sp):
     w = graphgen.workload("knn10000", sources=64)
     g = w.graph
     G = sp.Graph.from_csr(g.offsets, g.targets, g.weights, reorder=False)
-    for rule, kw in [("rho", {"rho": 4096}), ("delta", {"delta": 1 << 11})]:
+    for rule, kw in [("rho", {"rho": 4096}), ("delta", {"delta": 1898, "tuning": {"teams": 64}})]:
         dist, st = sp.solve(G, w.sources, rule=rule, **kw)
         got = sp.to_numpy_u64(dist)
         print(f"knn10000 {rule} {kw}: teams={st['teams']} ms={st['device_ms']:.1f}", flush=True)
