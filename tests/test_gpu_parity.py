@@ -46,6 +46,8 @@ def assert_same(got, exp, what=""):
 
 
 RULES = [("rho", {"rho": 1}), ("rho", {"rho": 3}), ("rho", {"rho": 64}), ("rho", {"rho": 1 << 30}),
+         ("rho", {"rho": 8, "tuning": {"hub_defer_degree": 2, "hub_defer_div": 4}}),
+         ("rho", {"rho": 3, "tuning": {"hub_defer_degree": 1, "hub_defer_div": 0xFFFFFFFF}}),
          ("rho_exact", {"rho": 1}), ("rho_exact", {"rho": 7}), ("rho_exact", {"rho": 100}),
          ("delta", {"delta": 1}), ("delta", {"delta": 777}), ("delta", {"delta": 1 << 40}), ("bf", {}),
          ("min", {})]
