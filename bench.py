@@ -113,10 +113,14 @@ def kernel_sha() -> str:
 
 def traffic_key(rho: int, tuning) -> str:
     """Key of a configuration in the traffic file: rho, plus the hub-deferral
-    setting when there is one ("2097152:defer32/1000")."""
+    setting when there is one and a list divisor other than the default
+    ("2097152:defer32/1000", "2097152:defer32/1000:list256")."""
+    key = str(rho)
     if tuning and tuning.get("hub_defer_degree"):
-        return f"{rho}:defer{tuning['hub_defer_degree']}/{tuning['hub_defer_div']}"
-    return str(rho)
+        key += f":defer{tuning['hub_defer_degree']}/{tuning['hub_defer_div']}"
+    if tuning and tuning.get("list_divisor", 64) != 64:
+        key += f":list{tuning['list_divisor']}"
+    return key
 
 
 def load_traffic(workload: str, key: str):
@@ -333,8 +337,10 @@ def run_single(args, torch, sp, w):
         if args.rho:
             fixed = {"rho": args.rho}
         if args.defer:
-            deg, div = (int(x) for x in args.defer.split(","))
-            tuning = {"hub_defer_degree": deg, "hub_defer_div": div}
+            parts = [int(x) for x in args.defer.split(",")]
+            tuning = {"hub_defer_degree": parts[0], "hub_defer_div": parts[1]}
+            if len(parts) > 2:
+                tuning["list_divisor"] = parts[2]
         elif sweep and args.defer_sweep and args.workload == "rmat24":
             # Hub deferral: the autotuner's candidates around the fastest rho
             # of the paper's rule; the timed solves use the fastest of all.
@@ -342,10 +348,21 @@ def run_single(args, torch, sp, w):
             for rho, deg, div in at.defer_candidates(fixed["rho"]):
                 defer_sweep.append(sweep_point(rho, {"hub_defer_degree": deg, "hub_defer_div": div}))
             best_d = min(defer_sweep, key=lambda r: r["ms"])
+            # The explicit-list switch around the best setting (the
+            # autotuner's next knob): a list kept only for smaller queues
+            # suits the deferred queue, which stays large for longer.
+            base_tun = {"hub_defer_degree": best_d["hub_defer"]["degree"], "hub_defer_div": best_d["hub_defer"]["div"]}
+            for ld in (16, 256):
+                r = sweep_point(best_d["rho"], {**base_tun, "list_divisor": ld})
+                r["list_divisor"] = ld
+                defer_sweep.append(r)
+            best_d = min(defer_sweep, key=lambda r: r["ms"])
             if best_d["ms"] < min(sweep, key=lambda r: r["ms"])["ms"] and not args.rho:
                 fixed = {"rho": best_d["rho"]}
                 tuning = {"hub_defer_degree": best_d["hub_defer"]["degree"],
                           "hub_defer_div": best_d["hub_defer"]["div"]}
+                if "list_divisor" in best_d:
+                    tuning["list_divisor"] = best_d["list_divisor"]
         if tuning:
             fixed["tuning"] = tuning
     else:
@@ -408,6 +425,7 @@ def run_single(args, torch, sp, w):
               **{k: v for k, v in fixed.items() if k != "tuning"},
               "hub_defer": ({"degree": tuning["hub_defer_degree"], "div": tuning["hub_defer_div"]}
                             if tuning else None),
+              "list_divisor": (tuning or {}).get("list_divisor", 64),
               "steps_per_solve": int(steps_total // args.steps),
               "edges_relaxed_per_solve": int(edges // args.steps),
               "writemin_success_per_solve": int(successes // args.steps),
@@ -426,7 +444,8 @@ def run_single(args, torch, sp, w):
     if defer_sweep:
         bd = min(defer_sweep, key=lambda r: r["ms"])
         res["hub_defer_sweep"] = {
-            "per_setting": defer_sweep, "fastest": {k: bd[k] for k in ("rho", "hub_defer", "ms")},
+            "per_setting": defer_sweep,
+            "fastest": {k: bd[k] for k in ("rho", "hub_defer", "ms", "list_divisor") if k in bd},
             "what": ("rho with hub deferral (vertices of out-degree >= degree extracted only at keys up to the "
                      "sampled (rho / div)-th key), one solve per source each; the timed solves use the fastest "
                      "configuration of both sweeps (fewer arcs relaxed for the same distances, so GTEPS and the "
@@ -848,8 +867,9 @@ def main():
     ap.add_argument("--sweep", default="16,17,18,19,20,21,22", metavar="LOG2_LIST",
                     help="rho values (log2) timed first, one solve per source each; the timed solves use the "
                          "fastest ('' = no sweep)")
-    ap.add_argument("--defer", default="", metavar="DEGREE,DIV",
-                    help="hub deferral for the timed solves (skips the deferral sweep)")
+    ap.add_argument("--defer", default="", metavar="DEGREE,DIV[,LIST_DIVISOR]",
+                    help="hub deferral (and optionally the explicit-list divisor) for the timed solves "
+                         "(skips the deferral sweep)")
     ap.add_argument("--no-defer-sweep", dest="defer_sweep", action="store_false",
                     help="time the fastest rho of the paper's rule only")
     ap.add_argument("--no-ceilings", action="store_true",

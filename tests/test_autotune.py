@@ -132,7 +132,7 @@ def defer_model(cfg):
 
 def test_hub_deferral_searched_with_rho():
     assert at.defer_candidates(1 << 10)[:3] == [(1 << 10, 32, 1000), (1 << 10, 64, 300), (1 << 10, 128, 100)]
-    assert len(at.defer_candidates(1 << 10)) == 9 and at.defer_candidates(8)[-1] == (32, 128, 100)
+    assert len(at.defer_candidates(1 << 10)) == 12 and at.defer_candidates(8)[-1] == (64, 128, 100)
     assert at.has_hubs([0, 1, 2, 3, 4, 5]) and not at.has_hubs([9, 9, 9, 9, 9]) and not at.has_hubs(None)
     tu = at.Tuner(measure=defer_model)
     cfg = tu.search(n=1 << 20, nsrc=1, w_median=1, rules=("rho",), hubs=True)
