@@ -305,8 +305,10 @@ def test_tournament_tree_queue_parity(sp):
         s = int(rng.integers(0, g.n))
         exp = ref(g, s)
         G = sp.Graph.from_csr(g.offsets, g.targets, g.weights)
-        for rule, kw in RULES:
-            for tun in (TREE, dict(queue=1, teams=8)):
+        for rule, kw0 in RULES:
+            for tun0 in (TREE, dict(queue=1, teams=8)):
+                kw = {k: v for k, v in kw0.items() if k != "tuning"}
+                tun = {**kw0.get("tuning", {}), **tun0}
                 dist, _ = sp.solve(G, [s, 0], rule=rule, seed=i, tuning=tun, **kw)
                 assert_same(sp.to_numpy_u64(dist)[0], exp, f"tree, graph {i} n={g.n} {rule} {kw} {tun}")
                 assert_same(sp.to_numpy_u64(dist)[1], ref(g, 0), f"tree, graph {i} source 0 {rule} {kw} {tun}")
