@@ -718,6 +718,7 @@ def run_serve(args, torch, sp):
     serve_teams = [int(x) for x in args.serve_teams.split(",")]
     serve_bpc = [int(x) for x in args.serve_bpc.split(",")]
     serve_gmax = [int(x) for x in args.serve_group_max.split(",")]
+    serve_gmin = [int(x) for x in args.serve_group_min.split(",")]
     # The admission budget, split between the two servers in proportion to
     # their grids.
     budget = int(args.serve_budget_gib * (1 << 30))
@@ -730,7 +731,7 @@ def run_serve(args, torch, sp):
         makespan, stats, most rows in use)."""
         servers = [sp.BudgetServer(G[k], budgets[k], tuning={**(cfg_s[k].get("tuning") or {}),
                                                              "blocks_per_cu": serve_bpc[k], "teams": serve_teams[k],
-                                                             "group_max": serve_gmax[k]},
+                                                             "group_max": serve_gmax[k], "group_min": serve_gmin[k]},
                                    hash_rows=True, stream=side, **params(cfg_s[k])) for k in (0, 1)]
         ticket = [{}, {}]
         lat = np.zeros(count)
@@ -831,7 +832,7 @@ def run_serve(args, torch, sp):
         "config": {"workload": WORKLOADS["serve"], "queries": nq, "closed_loop_queries": nc,
                    "admission_budget_bytes": budgets, "result_rows": rowinfo["rows"],
                    "peak_rows_in_use": rowinfo["peak_rows_in_use"],
-                   "server_teams": serve_teams, "server_blocks_per_cu": serve_bpc, "server_group_max": serve_gmax,
+                   "server_teams": serve_teams, "server_blocks_per_cu": serve_bpc, "server_group_max": serve_gmax, "server_group_min": serve_gmin,
                    "served": [params(c) | {"tuning": c.get("tuning")} for c in cfg_s],
                    "plain": [params(c) | {"tuning": c.get("tuning")} for c in cfg_p]},
         "closed_loop": {"queries": nc, "plain_qps": round(rate_plain, 2), "served_qps": round(nc / span_s0, 2),
@@ -896,6 +897,9 @@ def main():
                     help="serving: most teams per request on the R-MAT and grid servers (0 = all of them; "
                          "half of each server by default, so a request that arrives while another runs "
                          "finds idle teams)")
+    ap.add_argument("--serve-group-min", default="4,4",
+                    help="serving: fewest teams per request on the R-MAT and grid servers (a request waits "
+                         "while fewer are idle rather than run on one or two teams)")
     ap.add_argument("--serve-teams", default="16,32",
                     help="serving: teams of the R-MAT and grid servers (with --serve-bpc 2,2 on 256 CUs: 16 "
                          "R-MAT teams of 32 workgroups, 32 grid teams of 16); a request takes a group of "

@@ -181,6 +181,9 @@ typedef struct {
                              SSSP_KEEP_ORDER and SSSP_BORROW_DEVICE). 0 = library default
                              (off), 0xFFFFFFFF = off */
   uint32_t hub_defer_div;   /* theta_h's rank divisor for hub_defer_degree (0 = default 10) */
+  uint32_t group_min;       /* serving only: the fewest teams a request is dispatched to (rounded
+                             down to a power of two, at most group_max); a request waits while
+                             fewer teams are idle rather than run on one or two of them (0 = 1) */
 } sssp_tuning;
 
 /* One record per step, written when params.trace is set. */

@@ -65,7 +65,7 @@ class sssp_tuning(ctypes.Structure):
                 ("local_budget", ctypes.c_uint32), ("super_sparse_degree", ctypes.c_uint32),
                 ("pull", ctypes.c_uint32), ("group_max", ctypes.c_uint32), ("queue", ctypes.c_uint32),
                 ("repeat_skip", ctypes.c_uint32), ("hub_defer_degree", ctypes.c_uint32),
-                ("hub_defer_div", ctypes.c_uint32)]
+                ("hub_defer_div", ctypes.c_uint32), ("group_min", ctypes.c_uint32)]
 
 
 class sssp_step_record(ctypes.Structure):

@@ -260,6 +260,7 @@ struct KArgs {
   uint64_t idle_ticks;         // longest wait for a request
   uint32_t* dev_closed;        // host: set to 1 once the launch takes no more requests (idle limit)
   uint32_t group_max;          // serving: most teams that solve one request together (a power of two)
+  uint32_t group_min;          // serving: fewest teams a request is dispatched to (a power of two <= group_max)
   const uint32_t* cancel;      // host: nonzero asks the solve to stop (asynchronous solves), or NULL
 };
 
@@ -1927,10 +1928,14 @@ __device__ __forceinline__ T ld_system(const T* p) {
 // runs under a grid lock, on the thread of whichever idle team holds it: for
 // each posted request not yet taken it picks k idle teams, k the largest
 // power of two (at most group_max) such that every waiting request still
-// finds a team (k = idle teams / waiting requests, rounded down), copies the
-// request out of the ring into the leader's control block, acknowledges the
-// ring entry and writes each member's mailbox. Few requests in flight thus
-// get most of the grid each; under load every team solves its own.
+// finds a team (k = idle teams / waiting requests, rounded down), but at
+// least group_min: a request waits while fewer teams are idle (a finished
+// group frees its teams soon, and a lone team would take many times longer);
+// it copies the request out of the ring into the leader's control block,
+// acknowledges the ring entry and writes each member's mailbox. Few requests
+// in flight thus get most of the grid each; under load every group solves
+// its own. group_min is at most the server's team count, so a request is
+// dispatched at the latest once every team is idle.
 
 __device__ bool grid_lock(const KArgs& a, unsigned* lk, bool try_once) {
   const long long t0 = wall_clock64();
@@ -1965,6 +1970,10 @@ __device__ __noinline__ void serve_dispatch(const KArgs& a, GridCtl* gc) {
     if (k < 1) k = 1;
     k = 1ull << (63 - __clzll((long long)k));  // a power of two
     if (k > a.group_max) k = a.group_max;
+    if (k < a.group_min) {
+      if (idle < a.group_min) break;  // wait for more idle teams
+      k = a.group_min;
+    }
     const ull e = nq % a.ring_cap;
     const int32_t src = ld_system(&a.req[2 * e]);
     const uint32_t row = (uint32_t)ld_system(&a.req[2 * e + 1]);
@@ -3449,6 +3458,11 @@ sssp_status launch_server(sssp_graph* g, sssp_server* s, uint64_t* dist_rows, ui
     uint32_t p2 = 1;
     while (p2 * 2 <= gm) p2 *= 2;
     a.group_max = p2;
+    // group_min: a power of two, at most group_max (hence at most the team count).
+    const uint32_t gn = s->L.tu.group_min ? std::min(s->L.tu.group_min, p2) : 1u;
+    uint32_t q2 = 1;
+    while (q2 * 2 <= gn) q2 *= 2;
+    a.group_min = q2;
   }
   a.idle_ticks = g->tick_khz * (uint64_t)(idle_ms ? idle_ms : 60000);
   a.tlimit += a.idle_ticks;  // team members wait at their barrier while a request is awaited

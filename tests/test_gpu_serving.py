@@ -73,7 +73,7 @@ def test_row_hash_matches_definition(sp, torch_cuda):
         assert sp.row_hash(t) == np_row_hash(d), n
 
 
-@pytest.mark.parametrize("case", ["rmat", "road", "rmat-tree", "rmat-fixed-teams", "rmat-defer"])
+@pytest.mark.parametrize("case", ["rmat", "road", "rmat-tree", "rmat-fixed-teams", "rmat-defer", "rmat-group-min"])
 def test_server_matches_oracle(sp, torch_cuda, side_stream, case):
     torch = torch_cuda
     if case.startswith("rmat"):
@@ -84,6 +84,8 @@ def test_server_matches_oracle(sp, torch_cuda, side_stream, case):
             kw["tuning"] = {"queue": 1}  # tournament-tree LaB-PQ (Sec. 4.2)
         if case == "rmat-fixed-teams":
             kw["tuning"] = {"group_max": 1}  # one team per request
+        if case == "rmat-group-min":
+            kw["tuning"] = {"group_min": 4, "group_max": 8}  # requests wait for four idle teams
         if case == "rmat-defer":
             kw["tuning"] = {"hub_defer_degree": 16, "hub_defer_div": 100}  # hub deferral, per-group rho
     else:
