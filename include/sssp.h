@@ -393,7 +393,9 @@ sssp_status sssp_row_hash(const uint64_t* dist, int64_t n, void* stream, uint64_
  * running batch one by one. The group is elastic: k idle teams, k the largest
  * power of two such that every waiting request still finds a team (at most
  * tuning.group_max), so a request that arrives at a quiet server gets most of
- * the grid, and under load each team solves its own request.
+ * the grid, and under load each team solves its own request; with
+ * tuning.group_min, a request waits until at least that many teams are idle
+ * instead of running on one or two of them.
  *
  * Two ways to admit requests:
  *   - sssp_server_start: the caller owns `rows` result rows and names the row
