@@ -177,8 +177,14 @@ class Graph:
 
 
 def make_tuning(**kw) -> sssp_tuning:
+    """An sssp_tuning with the given fields set (the rest zero: library
+    defaults). Unknown field names raise ValueError (a ctypes structure would
+    otherwise take them as plain attributes and pass nothing on)."""
+    names = {f for f, _ in sssp_tuning._fields_}
     t = sssp_tuning()
     for k, v in kw.items():
+        if k not in names:
+            raise ValueError(f"unknown tuning field {k!r}; known: {', '.join(sorted(names))}")
         setattr(t, k, int(v))
     return t
 

@@ -205,3 +205,12 @@ def test_borrow_needs_device_input():
     rc, h = _create(2, 2, off, tgt, w, N.SSSP_INPUT_HOST | N.SSSP_BORROW_DEVICE)
     assert rc == N.SSSP_ERR_INVALID_ARGUMENT and h is None
     assert "BORROW" in N.sssp_last_error()
+
+
+def test_tuning_fields_by_name():
+    import paper_2105_06145_amd as sp
+    t = sp.make_tuning(hub_defer_degree=64, hub_defer_div=300, group_min=4, local_budget=8192)
+    assert (t.hub_defer_degree, t.hub_defer_div, t.group_min, t.local_budget) == (64, 300, 4, 8192)
+    assert t.teams == 0 and t.queue == 0  # the rest: library defaults
+    with pytest.raises(ValueError, match="group_mn"):
+        sp.make_tuning(group_mn=4)
